@@ -1,0 +1,404 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each checks a property that a
+plausible mistake (a dropped term, a wrong sign or index, a transposed operand,
+a wrong weight) would break -- exact integer arithmetic, conservation laws of
+linear binning, an independent formulation of the same sums, exact reproduction
+of linear functions by a local-linear fit, unbinned least squares by a library
+solver, closed-form eigenpairs.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from fpca_synth import grid_points, fourier_1d, fold_assignment
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_irregular(rng, d, n, Nlo, Nhi, dtype=np.float64):
+    Ni = rng.integers(Nlo, Nhi + 1, size=n)
+    off = np.concatenate([[0], np.cumsum(Ni)]).astype(np.int64)
+    t = rng.random((off[-1], d)).astype(dtype).astype(np.float64)
+    y = rng.standard_normal(off[-1])
+    return off, t, y
+
+
+# ------------------------------------------------------------------ P1 bin index
+def test_bin_index_exact_rational():
+    """Lower corner = min(floor(x (M-1)), M-2) computed in exact rational arithmetic."""
+    rng = np.random.default_rng(0)
+    for M in (2, 3, 17, 64, 101, 4097):
+        x = rng.random(2000).astype(np.float32).astype(np.float64)
+        x[:3] = [0.0, 1.0, np.float32(1.0 / 3.0)]
+        node, wt, lower = oracle.bin_corners((M,), x[:, None])
+        for xi, lo, w in zip(x[:200], lower[:200], wt[:200]):
+            u = Fraction(float(xi)) * (M - 1)
+            k = min(int(u), M - 2)
+            assert lo == k
+            assert w[1] == float(u - k) and w[0] == 1.0 - float(u - k)
+
+
+def test_bin_index_hand_cases():
+    M = 11
+    _, wt, lo = oracle.bin_corners((M,), np.array([[0.0], [1.0], [0.5], [0.05]]))
+    assert list(lo) == [0, 9, 5, 0]
+    assert wt[1].tolist() == [0.0, 1.0]          # x = 1 sits on the last node via rho = 1
+    assert wt[2].tolist() == [1.0, 0.0]
+    np.testing.assert_allclose(wt[3], [0.5, 0.5], rtol=0, atol=1e-15)
+    # float32(m/(M-1)) may land just below the node: then rho is ~1 on the lower cell
+    x = np.float64(np.float32(3.0 / 10.0))
+    _, wt, lo = oracle.bin_corners((M,), np.array([[x]]))
+    assert abs((lo[0] + wt[0][1]) / 10.0 - x) < 1e-15
+
+
+def test_domain_error():
+    with pytest.raises(ValueError):
+        oracle.bin_mean((8,), np.array([0, 2]), np.array([[0.2], [1.5]]), np.zeros(2))
+    with pytest.raises(ValueError):
+        oracle.bin_mean((8,), np.array([0, 1]), np.array([[np.nan]]), np.zeros(1))
+
+
+# ------------------------------------------------------------------ P2 conservation
+@pytest.mark.parametrize("d,M", [(1, (13,)), (2, (7, 9)), (3, (5, 4, 6))])
+def test_mean_binning_conserves_mass_and_first_moment(d, M):
+    rng = np.random.default_rng(d)
+    off, t, y = _tiny_irregular(rng, d, 9, 1, 12)
+    c, s, idx, cnt = oracle.bin_mean(M, off, t, y)
+    Ni = np.diff(off)
+    w = np.repeat(1.0 / Ni, Ni)
+    g = grid_points(M)
+    assert abs(c.sum() - len(Ni)) < 1e-12
+    assert abs(s.sum() - (w * y).sum()) < 1e-12
+    for k in range(d):
+        assert abs((c * g[:, k]).sum() - (w * t[:, k]).sum()) < 1e-12
+        assert abs((s * g[:, k]).sum() - (w * y * t[:, k]).sum()) < 1e-12
+    assert cnt.sum() == off[-1]
+    assert np.array_equal(np.bincount(idx, minlength=c.size), cnt)
+
+
+def test_cov_binning_conserves_mass_and_first_moment():
+    rng = np.random.default_rng(5)
+    d, M = 2, (5, 6)
+    off, t, y = _tiny_irregular(rng, d, 7, 1, 8)
+    C, G = oracle.bin_cov_pairs(M, off, t, y)
+    Ni = np.diff(off)
+    P = C.shape[0]
+    g = grid_points(M)
+    tot_c = tot_g = 0.0
+    fm_s = np.zeros(d)
+    fm_t = np.zeros(d)
+    for i in range(len(Ni)):
+        if Ni[i] < 2:
+            continue
+        w = 1.0 / (Ni[i] * (Ni[i] - 1))
+        a, b = off[i], off[i + 1]
+        for j in range(a, b):
+            for l in range(a, b):
+                if j != l:
+                    tot_c += w
+                    tot_g += w * y[j] * y[l]
+                    fm_s += w * t[j]
+                    fm_t += w * t[l]
+    assert abs(C.sum() - (Ni >= 2).sum()) < 1e-12 and abs(C.sum() - tot_c) < 1e-12
+    assert abs(G.sum() - tot_g) < 1e-12
+    for k in range(d):
+        assert abs((C * g[:, k][:, None]).sum() - fm_s[k]) < 1e-12
+        assert abs((C * g[:, k][None, :]).sum() - fm_t[k]) < 1e-12
+
+
+# ------------------------------------------------------------------ P3 identities
+@pytest.mark.parametrize("d,M", [(1, (9,)), (2, (5, 4)), (3, (3, 4, 3))])
+def test_pair_loops_equal_gram_identity(d, M):
+    rng = np.random.default_rng(10 + d)
+    off, t, y = _tiny_irregular(rng, d, 11, 1, 9)
+    folds = fold_assignment(11, 3, seed=3)
+    for fs in (-1, 0, 2):
+        C1, G1, Q1, n1 = oracle.bin_cov_pairs(M, off, t, y, folds, fs, want_Q=True, want_cnt=True)
+        C2, G2, Q2, n2 = oracle.bin_cov_identity(M, off, t, y, folds, fs, want_Q=True, want_cnt=True)
+        for A, B in ((C1, C2), (G1, G2), (Q1, Q2)):
+            assert np.abs(A - B).max() <= 1e-13 * max(1.0, np.abs(A).max())
+        assert np.array_equal(n1, n2)
+    # fold additivity (integers exact, values to rounding)
+    Ct, Gt, _, nt = oracle.bin_cov_pairs(M, off, t, y, want_Q=True, want_cnt=True)
+    parts = [oracle.bin_cov_pairs(M, off, t, y, folds, f, want_Q=True, want_cnt=True) for f in range(3)]
+    assert np.array_equal(sum(p[3] for p in parts), nt)
+    assert np.abs(sum(p[0] for p in parts) - Ct).max() < 1e-14
+    assert np.abs(sum(p[1] for p in parts) - Gt).max() < 1e-13
+
+
+def test_common_grid_closed_form():
+    """Observations at all P nodes: C = n/(P(P-1)) off the diagonal, 0 on it, and
+    G = Y^T Y/(P(P-1)) with the diagonal removed."""
+    rng = np.random.default_rng(3)
+    M = (4, 3)
+    P = 12
+    n = 5
+    Y = rng.standard_normal((n, P))
+    pts = grid_points(M)
+    off = np.arange(n + 1, dtype=np.int64) * P
+    t = np.tile(pts, (n, 1))
+    C, G = oracle.bin_cov_pairs(M, off, t, Y.reshape(-1))
+    c2, s2, C2, G2 = oracle.bin_common_grid(Y)
+    assert np.abs(C - C2).max() < 1e-15
+    assert np.abs(G - G2).max() < 1e-14
+    c, s, _, _ = oracle.bin_mean(M, off, t, Y.reshape(-1))
+    assert np.abs(c - c2).max() < 1e-15 and np.abs(s - s2).max() < 1e-14
+
+
+# ------------------------------------------------------------------ P4 linear reproduction
+@pytest.mark.parametrize("dims,h", [((23,), 0.13), ((9, 11), 0.3), ((5, 6, 7), 0.45),
+                                    ((7, 6, 7, 6), 0.4)])
+def test_local_linear_reproduces_linear_functions(dims, h):
+    """If g_p = c_p (a + b^T x_p) then b0(x) = a + b^T x at every node with an OK
+    status -- boundaries included (Fan & Gijbels' reproduction property)."""
+    rng = np.random.default_rng(len(dims))
+    P = int(np.prod(dims))
+    c = rng.random(P) + 0.05
+    c[rng.random(P) < 0.2] = 0.0
+    x = grid_points(dims)
+    a = 0.7
+    b = rng.standard_normal(len(dims))
+    g = c * (a + x @ b)
+    b0, st = oracle.smooth(dims, h, c, g)
+    ok = st == oracle.ST_OK
+    assert ok.mean() > 0.5
+    err = np.abs(b0[ok] - (a + x[ok] @ b)).max()
+    assert err < 1e-11, err
+
+
+def test_linear_reproduction_breaks_with_sign_error():
+    """Sanity: a linear function is NOT reproduced by the local-constant estimate
+    (so the pin above would catch a solver that drops the slope terms)."""
+    dims = (15,)
+    c = np.ones(15)
+    x = grid_points(dims)[:, 0]
+    g = c * (1 + 2 * x)
+    mom = oracle.smooth(dims, 0.3, c, g, want_moments=True)[2]
+    local_const = mom[:, 2] / mom[:, 0]
+    assert np.abs(local_const[0] - 1.0) > 0.05
+
+
+# ------------------------------------------------------------------ P7 brute force
+def _epan(u):
+    return np.where(np.abs(u) < 1, 1 - u * u, 0.0)
+
+
+def test_mean_bruteforce_unbinned_on_nodes():
+    """Observations on grid nodes: binned smoother == direct weighted least squares
+    of eq. (2.3) over the raw observations (numpy lstsq)."""
+    rng = np.random.default_rng(1)
+    M = (6, 5)
+    pts = grid_points(M)
+    n = 4
+    Ni = [3, 6, 2, 5]
+    off = np.concatenate([[0], np.cumsum(Ni)]).astype(np.int64)
+    t = pts[rng.integers(0, len(pts), off[-1])]
+    y = rng.standard_normal(off[-1])
+    h = 0.45
+    c, s, _, _ = oracle.bin_mean(M, off, t, y)
+    b0, st = oracle.smooth_mean(M, h, c, s)
+    w_obs = np.repeat(1.0 / np.asarray(Ni, float), Ni)
+    for p in range(len(pts)):
+        K = np.prod(_epan((t - pts[p]) / h), axis=1) * w_obs
+        sel = K > 0
+        if st[p] != oracle.ST_OK:
+            continue
+        X = np.column_stack([np.ones(sel.sum()), (t[sel] - pts[p])])
+        sw = np.sqrt(K[sel])
+        beta = np.linalg.lstsq(X * sw[:, None], y[sel] * sw, rcond=None)[0]
+        assert abs(beta[0] - b0[p]) < 1e-11 * max(1, abs(beta[0]))
+
+
+def test_cov_bruteforce_unbinned_on_nodes():
+    """Same for eq. (2.4): ordered pairs j != l with weight K K / (N_i (N_i - 1))."""
+    rng = np.random.default_rng(2)
+    M = (5,)
+    pts = grid_points(M)
+    Ni = [4, 3, 5, 2, 1]
+    off = np.concatenate([[0], np.cumsum(Ni)]).astype(np.int64)
+    t = pts[rng.integers(0, len(pts), off[-1])]
+    y = rng.standard_normal(off[-1])
+    h = 0.6
+    C, G = oracle.bin_cov_pairs(M, off, t, y)
+    b0, st = oracle.smooth_cov_raw(M, h, C, G)
+    S, T, W, Z = [], [], [], []
+    for i in range(len(Ni)):
+        if Ni[i] < 2:
+            continue
+        for j in range(off[i], off[i + 1]):
+            for l in range(off[i], off[i + 1]):
+                if j != l:
+                    S.append(t[j, 0]); T.append(t[l, 0])
+                    W.append(1.0 / (Ni[i] * (Ni[i] - 1))); Z.append(y[j] * y[l])
+    S, T, W, Z = map(np.asarray, (S, T, W, Z))
+    checked = 0
+    for p in range(len(pts)):
+        for q in range(len(pts)):
+            e = p * len(pts) + q
+            if st[e] != oracle.ST_OK:
+                continue
+            K = _epan((S - pts[p, 0]) / h) * _epan((T - pts[q, 0]) / h) * W
+            sel = K > 0
+            X = np.column_stack([np.ones(sel.sum()), S[sel] - pts[p, 0], T[sel] - pts[q, 0]])
+            sw = np.sqrt(K[sel])
+            beta = np.linalg.lstsq(X * sw[:, None], Z[sel] * sw, rcond=None)[0]
+            assert abs(beta[0] - b0[e]) < 1e-10 * max(1, abs(beta[0]))
+            checked += 1
+    assert checked > 10
+
+
+# ------------------------------------------------------------------ P8 WLS solver
+def test_wls_matches_library_solver_and_status_rules():
+    rng = np.random.default_rng(4)
+    D = 4
+    nm = oracle.num_moments(D)
+    moms = []
+    ref = []
+    for _ in range(50):
+        X = np.column_stack([np.ones(30), rng.standard_normal((30, D))])
+        w = rng.random(30)
+        yv = rng.standard_normal(30)
+        A = X.T @ (w[:, None] * X)
+        r = X.T @ (w * yv)
+        o = [A[0, 0]] + list(A[0, 1:]) + [A[1 + k, 1 + l] for k in range(D) for l in range(k, D)]
+        o += [r[0]] + list(r[1:])
+        moms.append(o)
+        ref.append(np.linalg.solve(A, r)[0])
+    b0, st, mp = oracle.wls_from_moments(D, np.array(moms))
+    assert (st == 0).all()
+    np.testing.assert_allclose(b0, ref, rtol=1e-10, atol=1e-12)
+    # EMPTY: S0 = 0
+    z = np.zeros(nm)
+    b0, st, _ = oracle.wls_from_moments(D, z[None])
+    assert st[0] == oracle.ST_EMPTY and np.isnan(b0[0])
+    # FALLBACK: all data on one line (singular) -> local constant T0/S0
+    X = np.column_stack([np.ones(10), np.zeros((10, D))])
+    X[:, 1] = np.linspace(-1, 1, 10)
+    yv = rng.standard_normal(10)
+    A = X.T @ X
+    r = X.T @ yv
+    o = [A[0, 0]] + list(A[0, 1:]) + [A[1 + k, 1 + l] for k in range(D) for l in range(k, D)]
+    o += [r[0]] + list(r[1:])
+    b0, st, _ = oracle.wls_from_moments(D, np.array([o]))
+    assert st[0] == oracle.ST_FALLBACK and abs(b0[0] - yv.mean()) < 1e-14
+
+
+# ------------------------------------------------------------------ P5, P10, P11
+def test_symmetry_constant_and_scaling():
+    rng = np.random.default_rng(6)
+    d, M = 1, (9,)
+    off, t, y = _tiny_irregular(rng, d, 12, 2, 10)
+    C, G = oracle.bin_cov_pairs(M, off, t, y)
+    assert np.abs(C - C.T).max() < 1e-15 and np.abs(G - G.T).max() < 1e-15
+    h = 0.3
+    Gh, st = oracle.smooth_cov_raw(M, h, C, G)
+    Gh = Gh.reshape(9, 9)
+    ok = (st.reshape(9, 9) == 0) & (st.reshape(9, 9).T == 0)
+    assert np.abs((Gh - Gh.T)[ok]).max() < 1e-12 * np.abs(Gh[ok]).max()
+    # constant data: mu = c, Ghat = c^2, Gamma = 0
+    yc = np.full_like(y, 1.7)
+    c, s, _, _ = oracle.bin_mean(M, off, t, yc)
+    mu, stm = oracle.smooth_mean(M, h, c, s)
+    C, G = oracle.bin_cov_pairs(M, off, t, yc)
+    Gh, st = oracle.smooth_cov_raw(M, h, C, G)
+    assert np.abs(mu[stm == 0] - 1.7).max() < 1e-13
+    assert np.abs(Gh[st == 0] - 1.7 ** 2).max() < 1e-12
+    Gam = oracle.assemble_cov(Gh.reshape(9, 9), mu)
+    okm = (st.reshape(9, 9) == 0)
+    assert np.abs(Gam[okm]).max() < 1e-12
+    # scaling: Y * a -> mu * a, Ghat * a^2; weights scaled by a constant leave b0 unchanged
+    a = -2.5
+    c1, s1, _, _ = oracle.bin_mean(M, off, t, y)
+    m1, _ = oracle.smooth_mean(M, h, c1, s1)
+    c2, s2, _, _ = oracle.bin_mean(M, off, t, a * y)
+    m2, _ = oracle.smooth_mean(M, h, c2, s2)
+    np.testing.assert_allclose(m2, a * m1, rtol=1e-12, atol=1e-14)
+    m3, _ = oracle.smooth_mean(M, h, 3.0 * c1, 3.0 * s1)
+    np.testing.assert_allclose(m3, m1, rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------------ P6, P9 eigen
+def _fourier_cov(M, index, lambdas):
+    pts = grid_points(M)
+    Phi = np.stack([np.prod([fourier_1d(a, pts[:, k]) for k, a in enumerate(tup)], axis=0)
+                    for tup in index], axis=1)
+    return Phi @ np.diag(lambdas) @ Phi.T, Phi
+
+
+@pytest.mark.parametrize("M,index", [((33,), [(2,), (1,), (4,)]),
+                                     ((17, 13), [(1, 1), (1, 2), (2, 1), (2, 2), (1, 3), (3, 1)])])
+def test_closed_form_eigenpairs_trapezoid(M, index):
+    """Gamma = sum_k lambda_k phi_k phi_k on the grid, trapezoid weights: the
+    matrixized eq. (3.1) has exactly these eigenpairs (discrete orthonormality of
+    the Fourier basis under the trapezoid rule)."""
+    lambdas = 2.0 ** -np.arange(1, len(index) + 1)
+    Gam, Phi = _fourier_cov(M, index, lambdas)
+    om = oracle.quad_weights(M, rule="trapezoid")
+    k = len(index)
+    ev, phi, fve = oracle.eig_dense(Gam, om, k)
+    np.testing.assert_allclose(ev, lambdas, rtol=1e-12)
+    for j in range(k):
+        err = min(np.abs(phi[:, j] - Phi[:, j]).max(), np.abs(phi[:, j] + Phi[:, j]).max())
+        assert err < 1e-10
+    np.testing.assert_allclose(fve[-1], 1.0, rtol=1e-12)
+    # random projection is exact when rank <= r (Section 3.4's premise)
+    ev2, phi2, fve2 = oracle.eig_randomized(Gam, om, k, 4, 1, seed=7)
+    np.testing.assert_allclose(ev2, lambdas, rtol=1e-10)
+    for j in range(k):
+        assert np.abs(phi2[:, j] - phi[:, j]).max() < 1e-8
+    np.testing.assert_allclose(fve2, fve, rtol=1e-10)
+
+
+def test_randomized_full_rank_within_hmt_bound():
+    """Full-rank A: the range-finder residual obeys the Halko-Martinsson-Tropp
+    expected bound (Thm 10.5, q = 0) computed from the dense spectrum."""
+    rng = np.random.default_rng(9)
+    P = 200
+    U, _ = np.linalg.qr(rng.standard_normal((P, P)))
+    s = 1.0 / np.arange(1, P + 1) ** 1.5
+    A = (U * s) @ U.T
+    om = np.ones(P)
+    k, p = 5, 5
+    _, _, _, Q = oracle.eig_randomized(A, om, k, p, 0, seed=3, return_basis=True)
+    resid = np.linalg.norm(A - Q @ (Q.T @ A), 2)
+    r = k + p
+    bound = (1 + np.sqrt(k / (p - 1))) * s[k] + np.e * np.sqrt(r) / p * np.sqrt((s[k:] ** 2).sum())
+    assert resid <= bound
+
+
+def test_rng_published_values_and_normals():
+    want = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.startswith("0x")]
+    got = [int(x) for x in oracle.splitmix64(0, 3)]
+    assert got == want
+    z = oracle.normals(123, 200000)
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1) < 0.01
+    assert abs((z ** 3).mean()) < 0.03 and abs((z ** 4).mean() - 3) < 0.05
+
+
+# ------------------------------------------------------------------ P12 CV
+def test_binned_cv_equals_pairwise_on_nodes():
+    rng = np.random.default_rng(12)
+    M = (6,)
+    pts = grid_points(M)
+    Ni = [4, 5, 3, 6]
+    off = np.concatenate([[0], np.cumsum(Ni)]).astype(np.int64)
+    t = pts[rng.integers(0, 6, off[-1])]
+    y = rng.standard_normal(off[-1])
+    Ghat = rng.standard_normal((6, 6))
+    Ghat = Ghat + Ghat.T
+    C, G, Q = oracle.bin_cov_pairs(M, off, t, y, want_Q=True)
+    score = oracle.cv_score(Q, G, C, Ghat)
+    direct = 0.0
+    node = np.rint(t[:, 0] * 5).astype(int)
+    for i in range(len(Ni)):
+        w = 1.0 / (Ni[i] * (Ni[i] - 1))
+        for j in range(off[i], off[i + 1]):
+            for l in range(off[i], off[i + 1]):
+                if j != l:
+                    direct += w * (y[j] * y[l] - Ghat[node[j], node[l]]) ** 2
+    assert abs(score - direct) < 1e-12 * abs(direct)
