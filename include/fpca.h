@@ -1,0 +1,206 @@
+/*
+ * fpca.h -- C ABI of the MI355X (gfx950) library for the hot path of
+ * multi-dimensional functional principal component analysis
+ * (Chen & Jiang, "Multi-dimensional Functional Principal Component Analysis").
+ *
+ * Problem statement (paper Section 2, eqs. 2.1-2.2): curves i = 1..n, each
+ * observed at N_i points t_ij in a domain Omega inside [0,1]^d (d <= 3) with
+ * values Y_ij = X_i(t_ij) + noise. The library computes
+ *   - linear binning of the observations onto a regular grid (Section 3.2),
+ *   - the binned local-linear smoother of the mean (eq. 2.3),
+ *   - the same smoother of the raw covariance surface on the 2d-dimensional
+ *     grid and the covariance Gamma(s,t) = b0(s,t) - mu(s) mu(t) (eq. 2.4),
+ *   - the top eigenpairs of the matrixized covariance (Section 3.1, eq. 3.1)
+ *     by random projection (Section 3.4).
+ *
+ * Conventions shared by every call
+ *   Grid: M_k nodes per coordinate at m/(M_k-1), m = 0..M_k-1; P = prod_k M_k;
+ *   flat node index with the last coordinate fastest. A covariance array is
+ *   P x P row-major: entry (p, q) is the s-node p and t-node q.
+ *   Kernel: product Epanechnikov K(u) = prod_k (1 - u_k^2)_+ (paper Section
+ *   2.1 names the product Epanechnikov kernel), u_k = (y_k - x_k) / h_k.
+ *   Memory: every array argument is a caller-allocated, contiguous DEVICE
+ *   pointer unless marked "host". The library never frees or retains caller
+ *   pointers after the stream work of the call has completed. Scratch memory
+ *   is owned by the handle; it grows on demand and is released by
+ *   fpca_destroy.
+ *   Streams: work is queued on the handle's stream (fpca_set_stream); calls
+ *   return after queueing, except where a host output is written (they then
+ *   synchronize the stream).
+ *   Errors: argument checks are synchronous and return a negative code with a
+ *   message in fpca_last_error(). Observations outside [0,1]^d or NaN are
+ *   detected on the device: they are skipped and raise a flag that the next
+ *   fpca_sync (or a call that synchronizes) returns as FPCA_ERR_DOMAIN.
+ *   Per-node numerical trouble in a smoother is not an error: it is reported
+ *   in `status` (FPCA_STATUS_*).
+ *   Handles are not thread-safe: use one handle per host thread.
+ */
+#ifndef FPCA_H
+#define FPCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fpca_context *fpca_handle;
+
+/* Return codes. */
+#define FPCA_OK 0
+#define FPCA_ERR_INVALID_ARG (-1)
+#define FPCA_ERR_DOMAIN (-2)      /* an observation outside [0,1]^d, or NaN */
+#define FPCA_ERR_UNSUPPORTED (-3) /* a size, dtype or precision combination not built */
+#define FPCA_ERR_WORKSPACE (-4)   /* scratch allocation failed or exceeded its limit */
+#define FPCA_ERR_DEVICE (-5)      /* a HIP runtime error */
+
+/* Per-node status of a smoother (the weighted least-squares solve). */
+#define FPCA_STATUS_OK 0       /* b0 of the local-linear fit */
+#define FPCA_STATUS_FALLBACK 1 /* singular or near-singular system: b0 = T0/S0, the local-constant fit */
+#define FPCA_STATUS_EMPTY 2    /* no data in the window: b0 = NaN */
+
+/* Binning kinds, designs, storage dtypes, compute precisions, kernels. */
+#define FPCA_BIN_MEAN 0
+#define FPCA_BIN_COV 1
+#define FPCA_IRREGULAR 0
+#define FPCA_COMMON_GRID 1
+#define FPCA_F64 0
+#define FPCA_F32 1
+#define FPCA_PREC_F64 0
+#define FPCA_PREC_F32 1
+#define FPCA_PREC_BF16X3 2
+#define FPCA_K_EPANECHNIKOV 0
+
+/* Regular grid over the bounding rectangle [0,1]^d (Section 3.1): d in 1..3,
+ * M[k] >= 2 nodes per coordinate. mask: optional device array of P bytes,
+ * nonzero where a node lies in Omega; NULL means Omega is the rectangle. */
+typedef struct {
+  int d;
+  int M[3];
+  const uint8_t *mask;
+} fpca_grid;
+
+/* Handle on device `device` (a HIP device ordinal), using the null stream
+ * until fpca_set_stream is called. */
+int fpca_create(fpca_handle *handle, int device);
+int fpca_destroy(fpca_handle handle);
+/* stream: a hipStream_t of the handle's device, passed as void*. */
+int fpca_set_stream(fpca_handle handle, void *stream);
+/* Waits for the handle's stream; returns FPCA_ERR_DOMAIN (and clears the flag)
+ * if a binning call met an observation outside [0,1]^d since the last sync. */
+int fpca_sync(fpca_handle handle);
+/* Message of the last nonzero code returned on this host thread. */
+const char *fpca_last_error(void);
+
+/*
+ * fpca_bin -- linear binning (Section 3.2; the weights of eqs. 2.3 and 2.4).
+ * Each observation point spreads onto its 2^d surrounding grid nodes with
+ * multilinear weights W_p(t): per coordinate u = t*(M-1) (one FP64 multiply),
+ * lower node k = min(floor(u), M-2), weights 1-(u-k) and u-k.
+ *
+ * kind = FPCA_BIN_MEAN (eq. 2.3, curve weight w_i = 1/N_i):
+ *   weights[p] = sum_i w_i sum_j W_p(t_ij)         (P entries)
+ *   sums[p]    = sum_i w_i sum_j W_p(t_ij) Y_ij
+ *   sq_sums[p] = sum_i w_i sum_j W_p(t_ij) Y_ij^2  (optional; the responses of eq. 2.5)
+ * kind = FPCA_BIN_COV (eq. 2.4, ordered pairs j != l, w_i = 1/(N_i(N_i-1)),
+ *   curves with N_i < 2 contribute nothing):
+ *   weights[p,q] = sum_i w_i sum_{j!=l} W_p(t_ij) W_q(t_il)   (P x P)
+ *   sums[p,q]    = ... times Y_ij Y_il
+ *   sq_sums[p,q] = ... times (Y_ij Y_il)^2  (optional; used by cross-validation)
+ *   With folds (fold_of_curve != NULL, n_folds >= 1) each of these arrays holds
+ *   n_folds+1 consecutive P x P slabs: slab 0 over all curves, slab f+1 over the
+ *   curves of fold f only.
+ *
+ * design = FPCA_IRREGULAR: offsets[n+1] (int64, offsets[0] = 0, nondecreasing)
+ *   delimit curve i's observations; t is N x d row-major and y has N entries,
+ *   N = offsets[n], both of storage dtype `dtype`.
+ * design = FPCA_COMMON_GRID: every curve is observed at all P nodes; offsets and
+ *   t must be NULL and y is the n x P row-major matrix of values. The pair
+ *   weights are then n/(P(P-1)) off the diagonal and 0 on it.
+ * dtype: FPCA_F64 or FPCA_F32 storage of t, y and every value output.
+ * prec (kind = COV only, the Gram product): FPCA_PREC_F64 (dtype F64),
+ *   FPCA_PREC_F32 (FP32 products, FP32 accumulation) or FPCA_PREC_BF16X3
+ *   (each FP32 operand split into bf16 hi + lo, three bf16 products, FP32
+ *   accumulation). Ignored for kind = MEAN.
+ * bin_index: optional, N int32 flat lower-corner node of each observation
+ *   (irregular only). cell_count: optional int64, P entries (MEAN: observations
+ *   per lower corner) or P x P (COV: ordered pairs per pair of lower corners,
+ *   over all curves with N_i >= 2). Both are exact integers.
+ * Returns FPCA_ERR_UNSUPPORTED for COV with P > 8192.
+ */
+int fpca_bin(fpca_handle handle, const fpca_grid *grid, int kind, int design, int dtype, int prec,
+             int64_t n, const int64_t *offsets, const void *t, const void *y,
+             const int32_t *fold_of_curve, int n_folds, void *weights, void *sums, void *sq_sums,
+             int32_t *bin_index, int64_t *cell_count);
+
+/*
+ * fpca_smooth_mean -- binned local-linear smoother of the mean (eq. 2.3):
+ * at every node x, b0 of the weighted least-squares fit of the binned sums
+ * with weights K((y-x)/h) and regressors (y-x)/h, solved in FP64:
+ *   [[S0, S1^T], [S1, S2]] beta = [T0; T1],  mu[x] = beta_0,
+ * with S0 = sum weights K, S1 = sum weights K u, S2 = sum weights K u u^T,
+ * T0 = sum sums K, T1 = sum sums K u over the window |y_k - x_k| <= h_k.
+ *   weights, sums: P entries of `dtype` (from fpca_bin kind MEAN).
+ *   bandwidth: host array of d bandwidths h_k > 0.
+ *   mu: P outputs of `dtype`; status: optional P int8 (FPCA_STATUS_*).
+ * Status rule: EMPTY if S0 == 0; FALLBACK if a diagonal entry is 0 or the
+ * Jacobi-scaled Cholesky factorization has a pivot below 1e-10; else OK.
+ */
+int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const void *weights,
+                     const void *sums, int kernel, const double *bandwidth, void *mu,
+                     int8_t *status);
+
+/*
+ * fpca_smooth_cov -- the covariance (eq. 2.4): the same smoother on the
+ * 2d-dimensional grid of (s, t) pairs, applied to the pair weights C and raw
+ * products G from fpca_bin kind COV (slab 0), giving b0(s,t), then
+ *   gamma[p,q] = (b0(p,q) + b0(q,p))/2 - mu[p] mu[q],
+ * and gamma = 0 where node p or q lies outside the grid's mask (Section 3.1).
+ *   C: P x P pair weights, or NULL for a complete common-grid design, where the
+ *      weights are uniform off the diagonal and 0 on it (their scale does not
+ *      change b0).
+ *   G: P x P raw products. mu: P values of the mean on this grid, or NULL to
+ *      return the raw second-moment surface b0 (symmetrized) instead.
+ *   bandwidth: host array of d bandwidths; the s- and t-coordinates share them.
+ *   gamma: P x P output of `dtype`; status: optional P x P int8.
+ */
+int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const void *C,
+                    const void *G, const void *mu, int kernel, const double *bandwidth,
+                    void *gamma, int8_t *status);
+
+/*
+ * fpca_eig_randomized -- top-k eigenpairs of the matrixized covariance
+ * (Section 3.1): A = W^1/2 Gamma W^1/2 with quadrature weights w_p, by random
+ * projection (Section 3.4) read as a randomized range finder:
+ *   Omega_g = P x r standard normal test matrix, r = k + oversample;
+ *   Q = orth(A Omega_g); power_iters times: Q = orth(A Q), Q = orth(A Q);
+ *   B = Q^T A Q; B = U diag(theta) U^T; psi = Q U.
+ * The eigenvalues are the top k theta in descending order; eigenfunctions are
+ * rescaled as phi = psi / sqrt(w) so that sum_p w_p phi_p^2 = 1, with the sign
+ * chosen so that sum_p w_p phi_p > 0 (if that sum is below 1e-8 sum_p w_p |phi_p|,
+ * the lowest-index entry within a relative 1e-6 of max |phi| is made positive).
+ * fve[l] = sum_{m<=l} theta_m / sum of the positive theta over all r Ritz values.
+ * Test matrix: entry (p, j) is standard normal number j*P + p of stream `seed`,
+ * drawn by the Box-Muller cosine branch from two splitmix64 outputs.
+ *   gamma: P x P (P = prod grid->M) symmetric, `dtype`.
+ *   quad_w: optional device array of P FP64 weights; NULL means the Riemann
+ *     weights prod_k 1/(M_k-1), set to 0 outside the grid's mask.
+ *   prec: FPCA_PREC_F64 (dtype F64) or FPCA_PREC_F32 (FP32 products of A with
+ *     the basis, FP64 orthonormalization and Rayleigh-Ritz).
+ *   k >= 1, oversample >= 0, k + oversample <= min(64, P).
+ *   evals: host, k doubles. efuns: device, P x k column-major of `dtype`.
+ *   fve: host, k doubles, or NULL. Synchronizes the handle's stream.
+ */
+int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid *grid,
+                        const void *gamma, const double *quad_w, int k, int oversample,
+                        int power_iters, uint64_t seed, double *evals, void *efuns, double *fve);
+
+/* Standard normal numbers 0..count-1 of stream `seed` (the test-matrix
+ * generator above), FP64, into the device array out. */
+int fpca_rng_normal(fpca_handle handle, uint64_t seed, int64_t count, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPCA_H */

@@ -46,8 +46,13 @@ def lib():
         L.orc_num_moments.argtypes = [I]
         L.orc_splitmix64.argtypes = [ctypes.c_uint64, I64, P]
         L.orc_normals.argtypes = [ctypes.c_uint64, I64, P]
+        L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _p(a):

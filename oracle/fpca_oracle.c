@@ -22,6 +22,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_ERR_ARG (-1)
@@ -411,4 +414,13 @@ int orc_normals(uint64_t seed, int64_t count, double *out) {
     out[i] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
   }
   return ORC_OK;
+}
+
+/* Threads the OpenMP loops of this library use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

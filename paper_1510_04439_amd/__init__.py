@@ -1,0 +1,17 @@
+"""MI355X (gfx950) hot path of multi-dimensional FPCA (Chen & Jiang).
+
+The compute lives in the HIP library `libfpca.so` (C ABI declared in
+include/fpca.h). This package is its thin Python binding: `fpca_bin`,
+`fpca_smooth_mean`, `fpca_smooth_cov`, `fpca_eig_randomized` and the handle
+calls take torch tensors for device memory and marshal pointers and the
+current HIP stream. Nothing here computes; if the library is missing, every
+call raises.
+"""
+from ._binding import (  # noqa: F401
+    FPCA_OK, FPCA_ERR_INVALID_ARG, FPCA_ERR_DOMAIN, FPCA_ERR_UNSUPPORTED, FPCA_ERR_WORKSPACE,
+    FPCA_ERR_DEVICE, FPCA_STATUS_OK, FPCA_STATUS_FALLBACK, FPCA_STATUS_EMPTY, FPCA_BIN_MEAN,
+    FPCA_BIN_COV, FPCA_IRREGULAR, FPCA_COMMON_GRID, FPCA_F64, FPCA_F32, FPCA_PREC_F64,
+    FPCA_PREC_F32, FPCA_PREC_BF16X3, FPCA_K_EPANECHNIKOV, FpcaError, Grid, Handle, LIB_PATH,
+    EXPORTED_SYMBOLS, fpca_bin, fpca_eig_randomized, fpca_rng_normal, fpca_smooth_cov,
+    fpca_smooth_mean, load_library,
+)

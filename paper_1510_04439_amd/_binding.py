@@ -1,0 +1,189 @@
+"""ctypes binding of libfpca.so: argument marshalling only.
+
+Every array argument is a torch tensor on the handle's device (or None for an
+optional argument); host outputs (eigenvalues, FVE) are returned as numpy
+arrays. Work is queued on the current torch stream of that device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpca.so")
+
+FPCA_OK = 0
+FPCA_ERR_INVALID_ARG = -1
+FPCA_ERR_DOMAIN = -2
+FPCA_ERR_UNSUPPORTED = -3
+FPCA_ERR_WORKSPACE = -4
+FPCA_ERR_DEVICE = -5
+FPCA_STATUS_OK, FPCA_STATUS_FALLBACK, FPCA_STATUS_EMPTY = 0, 1, 2
+FPCA_BIN_MEAN, FPCA_BIN_COV = 0, 1
+FPCA_IRREGULAR, FPCA_COMMON_GRID = 0, 1
+FPCA_F64, FPCA_F32 = 0, 1
+FPCA_PREC_F64, FPCA_PREC_F32, FPCA_PREC_BF16X3 = 0, 1, 2
+FPCA_K_EPANECHNIKOV = 0
+
+EXPORTED_SYMBOLS = [
+    "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
+    "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
+]
+
+
+class FpcaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fpca error {code}: {msg}")
+        self.code = code
+
+
+class _GridC(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("M", ctypes.c_int * 3), ("mask", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    L.fpca_create.argtypes = [ctypes.POINTER(vp), i32]
+    L.fpca_destroy.argtypes = [vp]
+    L.fpca_set_stream.argtypes = [vp, vp]
+    L.fpca_sync.argtypes = [vp]
+    L.fpca_last_error.restype = ctypes.c_char_p
+    L.fpca_bin.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i32, i32, i64, vp, vp, vp, vp, i32,
+                           vp, vp, vp, vp, vp]
+    L.fpca_smooth_mean.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, i32,
+                                   ctypes.POINTER(ctypes.c_double), vp, vp]
+    L.fpca_smooth_cov.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, i32,
+                                  ctypes.POINTER(ctypes.c_double), vp, vp]
+    L.fpca_eig_randomized.argtypes = [vp, i32, i32, ctypes.POINTER(_GridC), vp, vp, i32, i32, i32, u64,
+                                      ctypes.POINTER(ctypes.c_double), vp,
+                                      ctypes.POINTER(ctypes.c_double)]
+    L.fpca_rng_normal.argtypes = [vp, u64, i64, vp]
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FpcaError(rc, load_library().fpca_last_error().decode())
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if not x.is_cuda:
+        raise ValueError("device tensor expected")
+    if not x.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return x.data_ptr()
+
+
+class Grid:
+    """Regular grid: d coordinates, M[k] nodes at m/(M_k-1); optional uint8 mask tensor."""
+
+    def __init__(self, M: Sequence[int], mask=None):
+        self.M = tuple(int(m) for m in M)
+        self.d = len(self.M)
+        self.mask = mask
+        self.P = int(np.prod(self.M))
+
+    def c(self) -> _GridC:
+        g = _GridC()
+        g.d = self.d
+        for k in range(3):
+            g.M[k] = self.M[k] if k < self.d else 1
+        g.mask = _ptr(self.mask)
+        return g
+
+
+class Handle:
+    """fpca_create / fpca_destroy around one device; binds the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.fpca_create(ctypes.byref(h), device))
+        self._h = h
+        self._torch = torch
+
+    @property
+    def ptr(self):
+        stream = self._torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fpca_set_stream(self._h, ctypes.c_void_p(stream)))
+        return self._h
+
+    def sync(self):
+        _check(load_library().fpca_sync(self.ptr))
+
+    def close(self):
+        if self._h:
+            load_library().fpca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fpca_bin(h: Handle, grid: Grid, kind: int, design: int, dtype: int, prec: int, n: int,
+             offsets, t, y, fold_of_curve, n_folds: int, weights, sums, sq_sums=None,
+             bin_index=None, cell_count=None):
+    g = grid.c()
+    _check(load_library().fpca_bin(h.ptr, ctypes.byref(g), kind, design, dtype, prec, int(n),
+                                   _ptr(offsets), _ptr(t), _ptr(y), _ptr(fold_of_curve), int(n_folds),
+                                   _ptr(weights), _ptr(sums), _ptr(sq_sums), _ptr(bin_index),
+                                   _ptr(cell_count)))
+
+
+def _bw(bandwidth, d):
+    arr = (ctypes.c_double * d)(*[float(b) for b in np.broadcast_to(np.asarray(bandwidth, float), (d,))])
+    return arr
+
+
+def fpca_smooth_mean(h: Handle, grid: Grid, dtype: int, weights, sums, kernel: int, bandwidth, mu,
+                     status=None):
+    g = grid.c()
+    _check(load_library().fpca_smooth_mean(h.ptr, ctypes.byref(g), dtype, _ptr(weights), _ptr(sums),
+                                           kernel, _bw(bandwidth, grid.d), _ptr(mu), _ptr(status)))
+
+
+def fpca_smooth_cov(h: Handle, grid: Grid, dtype: int, C, G, mu, kernel: int, bandwidth, gamma,
+                    status=None):
+    g = grid.c()
+    _check(load_library().fpca_smooth_cov(h.ptr, ctypes.byref(g), dtype, _ptr(C), _ptr(G), _ptr(mu),
+                                          kernel, _bw(bandwidth, grid.d), _ptr(gamma), _ptr(status)))
+
+
+def fpca_eig_randomized(h: Handle, dtype: int, prec: int, grid: Grid, gamma, quad_w, k: int,
+                        oversample: int, power_iters: int, seed: int, efuns):
+    """Returns (evals[k], fve[k]) as numpy arrays; eigenfunctions go to `efuns` (k x P tensor,
+    i.e. P x k column-major)."""
+    g = grid.c()
+    ev = (ctypes.c_double * k)()
+    fv = (ctypes.c_double * k)()
+    _check(load_library().fpca_eig_randomized(h.ptr, dtype, prec, ctypes.byref(g), _ptr(gamma),
+                                              _ptr(quad_w), k, oversample, power_iters,
+                                              ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ev, _ptr(efuns),
+                                              fv))
+    return np.array(ev[:]), np.array(fv[:])
+
+
+def fpca_rng_normal(h: Handle, seed: int, count: int, out):
+    _check(load_library().fpca_rng_normal(h.ptr, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(count),
+                                          _ptr(out)))

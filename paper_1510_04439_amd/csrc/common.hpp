@@ -1,0 +1,89 @@
+// Internal declarations of the gfx950 FPCA library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "fpca.h"
+
+struct fpca_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // One growable scratch arena; carved into sub-buffers per call.
+  void *ws = nullptr;
+  size_t ws_size = 0;
+  size_t ws_limit = 0;  // 0 = unlimited
+  // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
+  int *d_flags = nullptr;
+  int *h_flags = nullptr;  // pinned mirror
+  int num_cus = 256;
+};
+
+namespace fpca {
+
+int set_error(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+#define FPCA_HIP(call)                              \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return fpca::hip_fail(e_, #call); \
+  } while (0)
+
+#define FPCA_LAUNCH_CHECK(what)                             \
+  do {                                                      \
+    hipError_t e_ = hipGetLastError();                      \
+    if (e_ != hipSuccess) return fpca::hip_fail(e_, what);  \
+  } while (0)
+
+// Scratch arena: ensure at least `bytes`; returns FPCA_OK or an error.
+int ws_reserve(fpca_context *ctx, size_t bytes);
+
+// Bump allocator over the reserved arena (256-byte aligned carving).
+struct Carver {
+  char *base;
+  size_t off = 0;
+  size_t cap;
+  template <typename T>
+  T *take(size_t count) {
+    size_t b = (count * sizeof(T) + 255) & ~size_t(255);
+    if (off + b > cap) return nullptr;
+    T *p = reinterpret_cast<T *>(base + off);
+    off += b;
+    return p;
+  }
+};
+inline size_t carve_bytes(size_t count, size_t elem) { return (count * elem + 255) & ~size_t(255); }
+
+int check_handle(fpca_context *ctx);
+int check_grid(const fpca_grid *g, int64_t *P);
+int set_device(fpca_context *ctx);
+
+// Grid geometry passed by value to kernels.
+struct GridDims {
+  int d;
+  int M[3];
+  int64_t stride[3];
+  int64_t P;
+};
+GridDims make_dims(const fpca_grid *g);
+
+// Launch helpers implemented in the .hip sources.
+int fill_f32(fpca_context *ctx, float *p, float v, int64_t n);
+int fill_f64(fpca_context *ctx, double *p, double v, int64_t n);
+int fill_i64(fpca_context *ctx, int64_t *p, int64_t v, int64_t n);
+int fill_bytes_zero(fpca_context *ctx, void *p, int64_t nbytes);
+
+// Symmetric rank-k product C = A^T A (A: K x N row-major, ld = N), written to
+// both triangles of the N x N output with ldc, scaled by `alpha`; entries on
+// the diagonal set to `diag_value` if zero_diag. FP32 operands on MFMA.
+int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, int64_t ldc,
+             float alpha, bool zero_diag, int prec);
+int syrk_f64(fpca_context *ctx, const double *A, int64_t K, int64_t N, double *C, int64_t ldc,
+             double alpha, bool zero_diag);
+
+}  // namespace fpca

@@ -1,0 +1,254 @@
+// Symmetric Gram products C = alpha * A^T A for the covariance binning
+// (the Gram form of the pair sums of eq. 2.4): A is K x N row-major (one row
+// per curve), C is N x N. Only tiles on or above the diagonal are computed;
+// each is also written transposed below the diagonal.
+#include "common.hpp"
+
+namespace fpca {
+
+namespace {
+
+constexpr int TB = 128;  // output tile edge per workgroup
+constexpr int TK = 16;   // K rows staged per LDS step
+constexpr int LDP = TB + 16;  // padded LDS row (bank spread for the 4 K-rows of an MFMA operand)
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline void tile_of(int id, int nb, int *bi, int *bj) {
+  int r = 0;
+  while (id >= nb - r) {
+    id -= nb - r;
+    ++r;
+  }
+  *bi = r;
+  *bj = r + id;
+}
+
+// bf16 split of an FP32 value: hi = round-to-nearest-even bf16(x), lo = bf16(x - hi).
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// FP32 operands; PREC 1: v_mfma_f32_16x16x4_f32 on FP32 values;
+// PREC 2: each operand split into bf16 hi/lo, products hi*hi + hi*lo + lo*hi
+// accumulated in FP32 on v_mfma_f32_16x16x16_bf16.
+template <bool VEC4, int PREC>
+__global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, int64_t K, int64_t N,
+                                                   float *__restrict__ C, int64_t ldc, float alpha,
+                                                   int zero_diag, int nb) {
+  __shared__ float As[TK][LDP];
+  __shared__ float Bs[TK][LDP];
+  int bi, bj;
+  tile_of(blockIdx.x, nb, &bi, &bj);
+  const bool diag_tile = (bi == bj);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = int64_t(bi) * TB, n0 = int64_t(bj) * TB;
+
+  float4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int lr = tid >> 4;        // staged K row 0..15
+  const int lc = (tid & 15) * 4;  // column group within a 64-wide half
+
+  for (int64_t k0 = 0; k0 < K; k0 += TK) {
+    const int64_t kr = k0 + lr;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int c = half * 64 + lc;
+      float va[4], vb[4];
+      if (VEC4) {
+        if (kr < K && m0 + c + 3 < N) {
+          float4 v = *reinterpret_cast<const float4 *>(A + kr * N + m0 + c);
+          va[0] = v.x; va[1] = v.y; va[2] = v.z; va[3] = v.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) va[e] = (kr < K && m0 + c + e < N) ? A[kr * N + m0 + c + e] : 0.f;
+        }
+        if (!diag_tile) {
+          if (kr < K && n0 + c + 3 < N) {
+            float4 v = *reinterpret_cast<const float4 *>(A + kr * N + n0 + c);
+            vb[0] = v.x; vb[1] = v.y; vb[2] = v.z; vb[3] = v.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) vb[e] = (kr < K && n0 + c + e < N) ? A[kr * N + n0 + c + e] : 0.f;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          va[e] = (kr < K && m0 + c + e < N) ? A[kr * N + m0 + c + e] : 0.f;
+          if (!diag_tile) vb[e] = (kr < K && n0 + c + e < N) ? A[kr * N + n0 + c + e] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[lr][c + e] = va[e];
+        if (!diag_tile) Bs[lr][c + e] = vb[e];
+      }
+    }
+    __syncthreads();
+    const float(*Bsrc)[LDP] = diag_tile ? As : Bs;
+    if (PREC == 1) {
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        float a[4], b[4];
+        const int krow = kk + (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As[krow][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bsrc[krow][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      // One 16x16x16 bf16 MFMA covers the whole 16-row K slab: lane supplies
+      // 4 consecutive K values (rows 4*(lane/16) .. +3) of its row/column.
+      typedef short short4_t __attribute__((ext_vector_type(4)));
+      short4_t ahi[4], alo[4], bhi[4], blo[4];
+      const int kb = 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float x = As[kb + e][wm * 64 + i * 16 + (lane & 15)];
+          unsigned short h = bf16_rne(x);
+          ahi[i][e] = (short)h;
+          alo[i][e] = (short)bf16_rne(x - bf16_to_f32(h));
+          float z = Bsrc[kb + e][wn * 64 + i * 16 + (lane & 15)];
+          unsigned short g = bf16_rne(z);
+          bhi[i][e] = (short)g;
+          blo[i][e] = (short)bf16_rne(z - bf16_to_f32(g));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // D layout of a 16x16 MFMA tile: lane l, element v -> row 4*(l/16)+v, column l%16.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t c = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (r < N && c < N) {
+          float val = alpha * acc[i][j][v];
+          if (zero_diag && r == c) val = 0.f;
+          C[r * ldc + c] = val;
+          if (!diag_tile) C[c * ldc + r] = val;
+        }
+      }
+}
+
+// Plain VALU Gram product for FP64 values and exact integer counts:
+// 64x64 output tile, 256 threads with 4x4 outputs each, all tiles computed.
+template <typename Tin, typename Tacc, typename Tout>
+__global__ __launch_bounds__(256) void k_gram_valu(const Tin *__restrict__ A, int64_t K, int64_t N,
+                                                    Tout *__restrict__ C, int64_t ldc, Tacc alpha,
+                                                    int zero_diag) {
+  __shared__ Tin As[16][64];
+  __shared__ Tin Bs[16][64];
+  const int tid = threadIdx.x;
+  const int64_t m0 = int64_t(blockIdx.y) * 64, n0 = int64_t(blockIdx.x) * 64;
+  const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+  Tacc acc[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = Tacc(0);
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      int r = e / 64, c = e % 64;
+      int64_t kr = k0 + r;
+      As[r][c] = (kr < K && m0 + c < N) ? A[kr * N + m0 + c] : Tin(0);
+      Bs[r][c] = (kr < K && n0 + c < N) ? A[kr * N + n0 + c] : Tin(0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 16; ++kk) {
+      Tacc a[4], b[4];
+      for (int i = 0; i < 4; ++i) a[i] = Tacc(As[kk][tr + i]);
+      for (int j = 0; j < 4; ++j) b[j] = Tacc(Bs[kk][tc + j]);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      int64_t r = m0 + tr + i, c = n0 + tc + j;
+      if (r < N && c < N) {
+        Tacc v = alpha * acc[i][j];
+        if (zero_diag && r == c) v = Tacc(0);
+        C[r * ldc + c] = Tout(v);
+      }
+    }
+}
+
+}  // namespace
+
+int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, int64_t ldc, float alpha,
+             bool zero_diag, int prec) {
+  if (N <= 0) return FPCA_OK;
+  int nb = int((N + TB - 1) / TB);
+  int tiles = nb * (nb + 1) / 2;
+  bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  if (prec == FPCA_PREC_BF16X3) {
+    if (vec)
+      hipLaunchKernelGGL((k_syrk_f32<true, 2>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb);
+    else
+      hipLaunchKernelGGL((k_syrk_f32<false, 2>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_syrk_f32<true, 1>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb);
+    else
+      hipLaunchKernelGGL((k_syrk_f32<false, 1>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb);
+  }
+  FPCA_LAUNCH_CHECK("syrk_f32");
+  return FPCA_OK;
+}
+
+int syrk_f64(fpca_context *ctx, const double *A, int64_t K, int64_t N, double *C, int64_t ldc, double alpha,
+             bool zero_diag) {
+  if (N <= 0) return FPCA_OK;
+  dim3 grid(unsigned((N + 63) / 64), unsigned((N + 63) / 64));
+  hipLaunchKernelGGL((k_gram_valu<double, double, double>), grid, dim3(256), 0, ctx->stream, A, K, N, C, ldc,
+                     alpha, int(zero_diag));
+  FPCA_LAUNCH_CHECK("syrk_f64");
+  return FPCA_OK;
+}
+
+// Exact integer Gram product of per-curve count rows (int32) into int64.
+int gram_i32(fpca_context *ctx, const int32_t *A, int64_t K, int64_t N, int64_t *C) {
+  if (N <= 0) return FPCA_OK;
+  dim3 grid(unsigned((N + 63) / 64), unsigned((N + 63) / 64));
+  hipLaunchKernelGGL((k_gram_valu<int32_t, int64_t, int64_t>), grid, dim3(256), 0, ctx->stream, A, K, N, C, N,
+                     int64_t(1), 0);
+  FPCA_LAUNCH_CHECK("gram_i32");
+  return FPCA_OK;
+}
+
+}  // namespace fpca

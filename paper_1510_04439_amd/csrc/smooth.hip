@@ -1,0 +1,453 @@
+// Binned local-linear smoothers of the mean (eq. 2.3) and of the raw
+// covariance on the 2d-dimensional grid (eq. 2.4).
+//
+// The moments of the weighted least-squares fit at a node x,
+//   S0 = sum w K, S1_k = sum w K u_k, S2_kl = sum w K u_k u_l,
+//   T0 = sum g K, T1_k = sum g K u_k,   K = prod_k (1 - u_k^2)_+, u = (y - x)/h,
+// factor over the coordinates because the kernel is a product: along each
+// coordinate in turn, every partial moment array is correlated with the 1-D
+// taps (1-u^2)u^j, j = 0..(remaining degree). This file holds the general
+// pass-per-coordinate engine for D <= 6 and the per-node FP64 solve.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace fpca {
+
+int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, const float *G,
+                        const double *bw, float *raw, int8_t *status, bool analytic_C);
+bool smooth_cov_fused_d2_supported(const fpca_grid *grid, const double *bw);
+
+namespace {
+
+constexpr int MAXD = 6;
+constexpr int MAXMOM = 1 + MAXD + MAXD * (MAXD + 1) / 2 + 1 + MAXD;  // 35
+
+struct MomArray {
+  int fam;  // 0: weights (S moments, degree <= 2); 1: sums (T moments, degree <= 1)
+  int e[MAXD];
+  int deg() const {
+    int s = 0;
+    for (int k = 0; k < MAXD; ++k) s += e[k];
+    return s;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int Mk, const T *__restrict__ src,
+                                               int nj, T *__restrict__ o0, T *__restrict__ o1, T *__restrict__ o2,
+                                               const T *__restrict__ taps, int R) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int xk = int((e / stride) % Mk);
+  const int lo = -min(R, xk), hi = min(R, Mk - 1 - xk);
+  const int W = 2 * R + 1;
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+  for (int m = lo; m <= hi; ++m) {
+    const T v = src[e + int64_t(m) * stride];
+    a0 += taps[m + R] * v;
+    if (nj > 1) a1 += taps[W + m + R] * v;
+    if (nj > 2) a2 += taps[2 * W + m + R] * v;
+  }
+  o0[e] = a0;
+  if (nj > 1) o1[e] = a1;
+  if (nj > 2) o2[e] = a2;
+}
+
+template <typename T>
+struct MomPtrs {
+  const T *p[MAXMOM];
+};
+
+}  // namespace
+
+// Solve [[S0, S1^T], [S1, S2]] beta = [T0; T1] in FP64 for b0 = beta_0.
+// Status: EMPTY if S0 <= 0 (b0 = NaN); FALLBACK (b0 = T0/S0) if a diagonal
+// entry is not positive or the Cholesky factorization of the Jacobi-scaled
+// (unit-diagonal) matrix meets a pivot that is not positive or below 1e-10;
+// OK otherwise. `m` holds the moments in the order S0, S1[D], S2 (upper
+// triangle, row by row), T0, T1[D].
+template <int D>
+__device__ inline double wls_b0(const double *m, int8_t *st) {
+  constexpr int n = D + 1;
+  double A[n][n], r[n], sc[n];
+  const double S0 = m[0];
+  const double T0 = m[1 + D + D * (D + 1) / 2];
+  if (!(S0 > 0.0)) {
+    *st = FPCA_STATUS_EMPTY;
+    return __builtin_nan("");
+  }
+  A[0][0] = S0;
+  r[0] = T0;
+  int q = 1 + D;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    A[0][1 + k] = A[1 + k][0] = m[1 + k];
+    r[1 + k] = m[2 + D + D * (D + 1) / 2 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int l = k; l < D; ++l) {
+      A[1 + k][1 + l] = A[1 + l][1 + k] = m[q++];
+    }
+  const double fb = T0 / S0;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    if (!(A[i][i] > 0.0)) {
+      *st = FPCA_STATUS_FALLBACK;
+      return fb;
+    }
+    sc[i] = 1.0 / sqrt(A[i][i]);
+  }
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    r[i] *= sc[i];
+#pragma unroll
+    for (int j = 0; j < n; ++j) A[i][j] *= sc[i] * sc[j];
+  }
+  // In-place Cholesky: lower triangle of A becomes L.
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    double dj = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= A[j][k] * A[j][k];
+    if (!(dj >= 1e-10)) {
+      *st = FPCA_STATUS_FALLBACK;
+      return fb;
+    }
+    const double ljj = sqrt(dj);
+    A[j][j] = ljj;
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+      A[i][j] = v * inv;
+    }
+  }
+  double z[n];
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    double v = r[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= A[i][k] * z[k];
+    z[i] = v / A[i][i];
+  }
+  double x0 = 0.0;
+#pragma unroll
+  for (int i = n - 1; i >= 0; --i) {
+    double v = z[i];
+#pragma unroll
+    for (int k = i + 1; k < n; ++k) v -= A[k][i] * r[k];
+    r[i] = v / A[i][i];  // reuse r as the solution
+    if (i == 0) x0 = r[0];
+  }
+  *st = FPCA_STATUS_OK;
+  return x0 * sc[0];
+}
+
+namespace {
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_wls(int64_t total, MomPtrs<T> mp, T *__restrict__ out,
+                                              int8_t *__restrict__ status) {
+  constexpr int NM = 1 + D + D * (D + 1) / 2 + 1 + D;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  double m[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) m[i] = double(mp.p[i][e]);
+  int8_t st;
+  const double b0 = wls_b0<D>(m, &st);
+  out[e] = T(b0);
+  if (status) status[e] = st;
+}
+
+// In-place covariance assembly on 32x32 tile pairs (I <= J):
+//   out(p,q) = (b(p,q) + b(q,p))/2 - mu_p mu_q, zero outside the mask.
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(int64_t P, T *__restrict__ A, const T *__restrict__ mu,
+                                                   const uint8_t *__restrict__ mask, int nb) {
+  __shared__ T ta[32][33];
+  __shared__ T tb[32][33];
+  int id = blockIdx.x, bi = 0;
+  while (id >= nb - bi) {
+    id -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + id;
+  const int64_t r0 = int64_t(bi) * 32, c0 = int64_t(bj) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    ta[rr][tx] = (r < P && c < P) ? A[r * P + c] : T(0);
+    const int64_t r2 = c0 + rr, c2 = r0 + tx;
+    tb[rr][tx] = (r2 < P && c2 < P) ? A[r2 * P + c2] : T(0);
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    if (r < P && c < P) {
+      T v = T(0.5) * (ta[rr][tx] + tb[tx][rr]);
+      if (mu) v -= mu[r] * mu[c];
+      if (mask && (!mask[r] || !mask[c])) v = T(0);
+      A[r * P + c] = v;
+    }
+    const int64_t r2 = c0 + rr, c2 = r0 + tx;
+    if (bi != bj && r2 < P && c2 < P) {
+      T v = T(0.5) * (tb[rr][tx] + ta[tx][rr]);
+      if (mu) v -= mu[r2] * mu[c2];
+      if (mask && (!mask[r2] || !mask[c2])) v = T(0);
+      A[r2 * P + c2] = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_offdiag_ones(T *A, int64_t P) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (; e < P * P; e += step) A[e] = (e / P == e % P) ? T(0) : T(1);
+}
+
+inline unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
+
+// 1-D taps (1 - u^2) u^j at offsets m = -R..R, u = m / (h (M-1)), zero for |u| >= 1.
+int tap_radius(double h, int M) { return int(std::floor(h * double(M - 1))); }
+
+template <typename T>
+int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, const T *w, const T *g, T *out,
+                   int8_t *status) {
+  int64_t total = 1;
+  int64_t stride[MAXD];
+  for (int k = 0; k < D; ++k) total *= dims[k];
+  stride[D - 1] = 1;
+  for (int k = D - 2; k >= 0; --k) stride[k] = stride[k + 1] * dims[k + 1];
+  int R[MAXD];
+  size_t tap_count = 0;
+  for (int k = 0; k < D; ++k) {
+    R[k] = tap_radius(h[k], dims[k]);
+    if (R[k] > 4096) return set_error(FPCA_ERR_UNSUPPORTED, "bandwidth spans too many grid steps");
+    tap_count += 3 * size_t(2 * R[k] + 1);
+  }
+  std::vector<T> taps_h(tap_count);
+  std::vector<size_t> tap_off(D);
+  {
+    size_t o = 0;
+    for (int k = 0; k < D; ++k) {
+      tap_off[k] = o;
+      const int W = 2 * R[k] + 1;
+      for (int j = 0; j < 3; ++j)
+        for (int m = -R[k]; m <= R[k]; ++m) {
+          const double u = double(m) / (h[k] * double(dims[k] - 1));
+          const double K = std::fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
+          taps_h[o + j * W + (m + R[k])] = T(K * std::pow(u, j));
+        }
+      o += 3 * W;
+    }
+  }
+  // Plan the passes: coordinates from the last (contiguous) to the first.
+  std::vector<std::vector<MomArray>> lists(D + 1);
+  lists[0].push_back(MomArray{0, {0}});
+  lists[0].push_back(MomArray{1, {0}});
+  size_t maxA = 0, maxB = 0;
+  for (int s = 0; s < D; ++s) {
+    const int k = D - 1 - s;
+    for (const MomArray &a : lists[s]) {
+      const int maxdeg = a.fam == 0 ? 2 : 1;
+      for (int j = 0; j <= maxdeg - a.deg(); ++j) {
+        MomArray b = a;
+        b.e[k] += j;
+        lists[s + 1].push_back(b);
+      }
+    }
+    if (s % 2 == 0)
+      maxA = std::max(maxA, lists[s + 1].size());
+    else
+      maxB = std::max(maxB, lists[s + 1].size());
+  }
+  const size_t bytesA = carve_bytes(maxA * size_t(total), sizeof(T));
+  const size_t bytesB = carve_bytes(maxB * size_t(total), sizeof(T));
+  const size_t bytesT = carve_bytes(tap_count, sizeof(T));
+  if (int rc = ws_reserve(ctx, bytesA + bytesB + bytesT)) return rc;
+  Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
+  T *bufA = cv.take<T>(maxA * size_t(total));
+  T *bufB = cv.take<T>(maxB * size_t(total));
+  T *taps = cv.take<T>(tap_count);
+  FPCA_HIP(hipMemcpyAsync(taps, taps_h.data(), tap_count * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+
+  std::vector<const T *> cur = {w, g};
+  for (int s = 0; s < D; ++s) {
+    const int k = D - 1 - s;
+    T *dst = (s % 2 == 0) ? bufA : bufB;
+    std::vector<const T *> next;
+    size_t o = 0;
+    for (size_t a = 0; a < lists[s].size(); ++a) {
+      const MomArray &m = lists[s][a];
+      const int nj = (m.fam == 0 ? 2 : 1) - m.deg() + 1;
+      T *outs[3] = {nullptr, nullptr, nullptr};
+      for (int j = 0; j < nj; ++j) {
+        outs[j] = dst + (o + j) * size_t(total);
+        next.push_back(outs[j]);
+      }
+      hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k], dims[k],
+                         cur[a], nj, outs[0], outs[1] ? outs[1] : outs[0], outs[2] ? outs[2] : outs[0],
+                         taps + tap_off[k], R[k]);
+      FPCA_LAUNCH_CHECK("moment pass");
+      o += nj;
+    }
+    cur.swap(next);
+  }
+  // Gather the final arrays in moment order.
+  MomPtrs<T> mp{};
+  const std::vector<MomArray> &fin = lists[D];
+  auto find = [&](int fam, const int *e) -> const T * {
+    for (size_t i = 0; i < fin.size(); ++i) {
+      if (fin[i].fam != fam) continue;
+      bool eq = true;
+      for (int k = 0; k < D; ++k) eq &= fin[i].e[k] == e[k];
+      if (eq) return cur[i];
+    }
+    return nullptr;
+  };
+  int q = 0;
+  int e[MAXD] = {0};
+  mp.p[q++] = find(0, e);
+  for (int k = 0; k < D; ++k) {
+    int ek[MAXD] = {0};
+    ek[k] = 1;
+    mp.p[q++] = find(0, ek);
+  }
+  for (int k = 0; k < D; ++k)
+    for (int l = k; l < D; ++l) {
+      int ek[MAXD] = {0};
+      ek[k] += 1;
+      ek[l] += 1;
+      mp.p[q++] = find(0, ek);
+    }
+  mp.p[q++] = find(1, e);
+  for (int k = 0; k < D; ++k) {
+    int ek[MAXD] = {0};
+    ek[k] = 1;
+    mp.p[q++] = find(1, ek);
+  }
+  for (int i = 0; i < q; ++i)
+    if (!mp.p[i]) return set_error(FPCA_ERR_DEVICE, "internal: moment %d missing", i);
+  switch (D) {
+#define WLS_CASE(DD)                                                                                        \
+  case DD:                                                                                                  \
+    hipLaunchKernelGGL((k_wls<T, DD>), dim3(nblk(total)), dim3(256), 0, ctx->stream, total, mp, out, status); \
+    break;
+    WLS_CASE(1)
+    WLS_CASE(2)
+    WLS_CASE(3)
+    WLS_CASE(4)
+    WLS_CASE(5)
+    WLS_CASE(6)
+#undef WLS_CASE
+    default:
+      return set_error(FPCA_ERR_UNSUPPORTED, "D=%d", D);
+  }
+  FPCA_LAUNCH_CHECK("wls");
+  return FPCA_OK;
+}
+
+int check_bw(const double *bw, int d) {
+  if (!bw) return set_error(FPCA_ERR_INVALID_ARG, "bandwidth is required");
+  for (int k = 0; k < d; ++k)
+    if (!(bw[k] > 0.0) || !std::isfinite(bw[k]))
+      return set_error(FPCA_ERR_INVALID_ARG, "bandwidth[%d] must be positive and finite", k);
+  return FPCA_OK;
+}
+
+template <typename T>
+int assemble(fpca_context *ctx, int64_t P, T *A, const T *mu, const uint8_t *mask) {
+  const int nb = int((P + 31) / 32);
+  hipLaunchKernelGGL(k_assemble<T>, dim3(unsigned(nb * (nb + 1) / 2)), dim3(256), 0, ctx->stream, P, A, mu, mask,
+                     nb);
+  FPCA_LAUNCH_CHECK("assemble");
+  return FPCA_OK;
+}
+
+template <typename T>
+int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, const T *G, const T *mu,
+                    const double *bw, T *gamma, int8_t *status) {
+  const GridDims gd = make_dims(grid);
+  const int64_t P = gd.P;
+  const int d = grid->d;
+  bool done = false;
+  if constexpr (sizeof(T) == 4) {
+    if (d == 2 && smooth_cov_fused_d2_supported(grid, bw)) {
+      if (int rc = smooth_cov_fused_d2(ctx, grid, C, G, bw, gamma, status, C == nullptr)) return rc;
+      done = true;
+    }
+  }
+  if (!done) {
+    int dims[MAXD];
+    double h[MAXD];
+    for (int k = 0; k < d; ++k) {
+      dims[k] = dims[k + d] = grid->M[k];
+      h[k] = h[k + d] = bw[k];
+    }
+    const T *Cuse = C;
+    if (!C) {
+      // complete common grid: uniform pair weights off the diagonal; kept in
+      // the output buffer's place until the smoother has read it
+      if (int rc = ws_reserve(ctx, 0)) return rc;
+      T *tmp = nullptr;
+      FPCA_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), sizeof(T) * P * P, ctx->stream));
+      hipLaunchKernelGGL(k_offdiag_ones<T>, dim3(nblk(P * P) > 65536 ? 65536 : nblk(P * P)), dim3(256), 0,
+                         ctx->stream, tmp, P);
+      FPCA_LAUNCH_CHECK("offdiag");
+      int rc = smooth_generic<T>(ctx, 2 * d, dims, h, tmp, G, gamma, status);
+      (void)hipFreeAsync(tmp, ctx->stream);
+      if (rc) return rc;
+    } else {
+      if (int rc = smooth_generic<T>(ctx, 2 * d, dims, h, Cuse, G, gamma, status)) return rc;
+    }
+  }
+  return assemble<T>(ctx, P, gamma, mu, grid->mask);
+}
+
+}  // namespace
+}  // namespace fpca
+
+using namespace fpca;
+
+extern "C" int fpca_smooth_mean(fpca_handle ctx, const fpca_grid *grid, int dtype, const void *weights,
+                                const void *sums, int kernel, const double *bandwidth, void *mu, int8_t *status) {
+  if (int rc = check_handle(ctx)) return rc;
+  int64_t P;
+  if (int rc = check_grid(grid, &P)) return rc;
+  if (kernel != FPCA_K_EPANECHNIKOV) return set_error(FPCA_ERR_UNSUPPORTED, "kernel %d", kernel);
+  if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (!weights || !sums || !mu) return set_error(FPCA_ERR_INVALID_ARG, "weights, sums and mu are required");
+  if (int rc = check_bw(bandwidth, grid->d)) return rc;
+  if (int rc = set_device(ctx)) return rc;
+  if (dtype == FPCA_F64)
+    return smooth_generic<double>(ctx, grid->d, grid->M, bandwidth, static_cast<const double *>(weights),
+                                  static_cast<const double *>(sums), static_cast<double *>(mu), status);
+  return smooth_generic<float>(ctx, grid->d, grid->M, bandwidth, static_cast<const float *>(weights),
+                               static_cast<const float *>(sums), static_cast<float *>(mu), status);
+}
+
+extern "C" int fpca_smooth_cov(fpca_handle ctx, const fpca_grid *grid, int dtype, const void *C, const void *G,
+                               const void *mu, int kernel, const double *bandwidth, void *gamma, int8_t *status) {
+  if (int rc = check_handle(ctx)) return rc;
+  int64_t P;
+  if (int rc = check_grid(grid, &P)) return rc;
+  if (kernel != FPCA_K_EPANECHNIKOV) return set_error(FPCA_ERR_UNSUPPORTED, "kernel %d", kernel);
+  if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (!G || !gamma) return set_error(FPCA_ERR_INVALID_ARG, "G and gamma are required");
+  if (P > (int64_t(1) << 15)) return set_error(FPCA_ERR_UNSUPPORTED, "covariance grid too large (P=%lld)", (long long)P);
+  if (int rc = check_bw(bandwidth, grid->d)) return rc;
+  if (int rc = set_device(ctx)) return rc;
+  if (dtype == FPCA_F64)
+    return smooth_cov_impl<double>(ctx, grid, static_cast<const double *>(C), static_cast<const double *>(G),
+                                   static_cast<const double *>(mu), bandwidth, static_cast<double *>(gamma), status);
+  return smooth_cov_impl<float>(ctx, grid, static_cast<const float *>(C), static_cast<const float *>(G),
+                                static_cast<const float *>(mu), bandwidth, static_cast<float *>(gamma), status);
+}

@@ -1,0 +1,362 @@
+"""GPU parity: every ABI call against the FP64 oracle on the same seeded inputs.
+
+Bars: integers (bin indices, counts) bit-exact; FP64 paths to 1e-10 normwise;
+FP32 paths to 1e-5 normwise (||x - ref||_inf <= 1e-5 ||ref||_inf over nodes
+whose status is OK on both sides); the BF16x3 Gram product to 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from fpca_synth import grid_points, make_c1, make_c2, fourier_1d, disk_time_mask, fold_assignment
+from tests._util import normwise_rel, rand_irregular, status_agreement
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a GPU"
+    return T
+
+
+@pytest.fixture(scope="module")
+def F(torch):
+    import paper_1510_04439_amd as F
+    F.load_library()
+    return F
+
+
+@pytest.fixture(scope="module")
+def h(F):
+    hh = F.Handle(0)
+    yield hh
+    hh.close()
+
+
+def dev(torch, a, dt=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dt is not None:
+        t = t.to(dt)
+    return t.to("cuda:0")
+
+
+def host(x):
+    return x.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------ RNG
+def test_rng_normal_matches_oracle(torch, F, h):
+    _say("rng")
+    n = 100_000
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    F.fpca_rng_normal(h, 7, n, out)
+    torch.cuda.synchronize()
+    ref = oracle.normals(7, n)
+    assert np.abs(host(out) - ref).max() < 1e-13
+
+
+# ------------------------------------------------------------------ binning
+@pytest.mark.parametrize("d,M,dt", [(1, (101,), "f64"), (2, (32, 32), "f32"), (3, (7, 9, 5), "f32"),
+                                    (2, (13, 17), "f64")])
+def test_bin_mean_parity(torch, F, h, d, M, dt):
+    _say(f"bin_mean d={d} M={M} {dt}")
+    rng = np.random.default_rng(100 + d)
+    npdt = np.float64 if dt == "f64" else np.float32
+    off, t, y = rand_irregular(rng, d, 300, 0, 60, npdt)
+    t[:4] = 0.0
+    t[4:8] = 1.0
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    P = int(np.prod(M))
+    c = torch.empty(P, dtype=tdt, device="cuda:0")
+    s = torch.empty_like(c)
+    s2 = torch.empty_like(c)
+    idx = torch.empty(len(y), dtype=torch.int32, device="cuda:0")
+    cnt = torch.empty(P, dtype=torch.int64, device="cuda:0")
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_MEAN, F.FPCA_IRREGULAR, F.FPCA_F64 if dt == "f64" else F.FPCA_F32,
+               F.FPCA_PREC_F64 if dt == "f64" else F.FPCA_PREC_F32, len(off) - 1, dev(torch, off),
+               dev(torch, t), dev(torch, y), None, 0, c, s, s2, idx, cnt)
+    h.sync()
+    rc, rs, ridx, rcnt = oracle.bin_mean(M, off, t.astype(np.float64), y.astype(np.float64))
+    _, rs2, _, _ = oracle.bin_mean(M, off, t.astype(np.float64), y.astype(np.float64) ** 2)
+    assert np.array_equal(host(idx), ridx)
+    assert np.array_equal(host(cnt), rcnt)
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert normwise_rel(host(c), rc) < tol
+    assert normwise_rel(host(s), rs) < tol
+    assert normwise_rel(host(s2), rs2) < tol
+
+
+@pytest.mark.parametrize("d,M,dt,nf", [(1, (21,), "f64", 0), (2, (9, 8), "f32", 3), (3, (5, 4, 6), "f32", 5),
+                                       (2, (16, 16), "f32", 0)])
+def test_bin_cov_parity(torch, F, h, d, M, dt, nf):
+    _say(f"bin_cov d={d} M={M} {dt} folds={nf}")
+    rng = np.random.default_rng(200 + d)
+    npdt = np.float64 if dt == "f64" else np.float32
+    n = 40
+    off, t, y = rand_irregular(rng, d, n, 0, 30, npdt)
+    folds = fold_assignment(n, nf, seed=5) if nf else None
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    P = int(np.prod(M))
+    ns = nf + 1 if nf else 1
+    C = torch.empty(ns, P, P, dtype=tdt, device="cuda:0")
+    G = torch.empty_like(C)
+    Q = torch.empty_like(C)
+    cnt = torch.empty(P, P, dtype=torch.int64, device="cuda:0")
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_IRREGULAR, F.FPCA_F64 if dt == "f64" else F.FPCA_F32,
+               F.FPCA_PREC_F64 if dt == "f64" else F.FPCA_PREC_F32, n, dev(torch, off), dev(torch, t),
+               dev(torch, y), dev(torch, folds) if nf else None, nf, C, G, Q, None, cnt)
+    h.sync()
+    t64, y64 = t.astype(np.float64), y.astype(np.float64)
+    tol = 1e-12 if dt == "f64" else 1e-5
+    for s in range(ns):
+        fs = -1 if s == 0 else s - 1
+        rC, rG, rQ, rn = oracle.bin_cov_pairs(M, off, t64, y64, folds, fs, want_Q=True, want_cnt=True)
+        assert normwise_rel(host(C[s]), rC) < tol, s
+        assert normwise_rel(host(G[s]), rG) < tol, s
+        assert normwise_rel(host(Q[s]), rQ) < tol, s
+        if s == 0:
+            assert np.array_equal(host(cnt), rn)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x3", 1e-4)])
+def test_bin_cov_common_grid(torch, F, h, prec, tol):
+    _say(f"bin_cov common {prec}")
+    rng = np.random.default_rng(7)
+    M = (20, 13)
+    P = 260
+    n = 333
+    Y = rng.standard_normal((n, P)).astype(np.float32)
+    C = torch.empty(P, P, dtype=torch.float32, device="cuda:0")
+    G = torch.empty_like(C)
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, F.FPCA_F32,
+               F.FPCA_PREC_F32 if prec == "f32" else F.FPCA_PREC_BF16X3, n, None, None, dev(torch, Y), None, 0,
+               C, G)
+    c = torch.empty(P, dtype=torch.float32, device="cuda:0")
+    s = torch.empty_like(c)
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_MEAN, F.FPCA_COMMON_GRID, F.FPCA_F32, F.FPCA_PREC_F32, n, None, None,
+               dev(torch, Y), None, 0, c, s)
+    h.sync()
+    rc, rs, rC, rG = oracle.bin_common_grid(Y.astype(np.float64))
+    assert normwise_rel(host(C), rC) < 1e-7
+    assert normwise_rel(host(G), rG) < tol
+    assert np.all(np.diag(host(G)) == 0)
+    assert normwise_rel(host(c), rc) < 1e-7 and normwise_rel(host(s), rs) < 1e-5
+
+
+def test_domain_error_reported(torch, F, h):
+    _say("domain")
+    off = np.array([0, 3], np.int64)
+    t = np.array([[0.2], [1.5], [0.4]], np.float32)
+    y = np.ones(3, np.float32)
+    c = torch.empty(9, dtype=torch.float32, device="cuda:0")
+    s = torch.empty_like(c)
+    F.fpca_bin(h, F.Grid((9,)), F.FPCA_BIN_MEAN, F.FPCA_IRREGULAR, F.FPCA_F32, F.FPCA_PREC_F32, 1,
+               dev(torch, off), dev(torch, t), dev(torch, y), None, 0, c, s)
+    with pytest.raises(F.FpcaError) as e:
+        h.sync()
+    assert e.value.code == F.FPCA_ERR_DOMAIN
+    h.sync()  # flag cleared
+
+
+# ------------------------------------------------------------------ smoothers
+def _smooth_case(rng, dims, sparse=0.2):
+    P = int(np.prod(dims))
+    w = rng.random(P) + 0.02
+    w[rng.random(P) < sparse] = 0.0
+    g = w * rng.standard_normal(P)
+    return w, g
+
+
+@pytest.mark.parametrize("M,hb,dt", [((101,), 0.1, "f64"), ((32, 32), 0.08, "f32"), ((16, 16, 16), 0.2, "f32"),
+                                     ((40,), 0.013, "f32"), ((9, 23), 0.3, "f64")])
+def test_smooth_mean_parity(torch, F, h, M, hb, dt):
+    _say(f"smooth_mean M={M} h={hb} {dt}")
+    rng = np.random.default_rng(len(M) * 10 + M[0])
+    w, g = _smooth_case(rng, M)
+    npdt = np.float64 if dt == "f64" else np.float32
+    w, g = w.astype(npdt), g.astype(npdt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    P = w.size
+    mu = torch.empty(P, dtype=tdt, device="cuda:0")
+    st = torch.empty(P, dtype=torch.int8, device="cuda:0")
+    F.fpca_smooth_mean(h, F.Grid(M), F.FPCA_F64 if dt == "f64" else F.FPCA_F32, dev(torch, w), dev(torch, g),
+                       F.FPCA_K_EPANECHNIKOV, hb, mu, st)
+    h.sync()
+    rb, rst, _, rmp = oracle.smooth(M, hb, w.astype(np.float64), g.astype(np.float64), want_moments=True)
+    bad, band = status_agreement(host(st), rst, rmp)
+    assert bad == 0
+    ok = (host(st) == 0) & (rst == 0)
+    tol = 1e-10 if dt == "f64" else 1e-5
+    assert normwise_rel(host(mu), rb, ok) < tol
+    fb = (host(st) == 1) & (rst == 1)
+    if fb.any():
+        assert normwise_rel(host(mu), rb, fb) < tol
+    assert np.all(np.isnan(host(mu)[rst == 2]))
+
+
+def _cov_inputs(rng, M, d):
+    """Pair weights and raw products on the 2d-grid from random curves (oracle binning)."""
+    off, t, y = rand_irregular(rng, d, 60, 2, 25, np.float64)
+    C, G = oracle.bin_cov_pairs(M, off, t, y)
+    return C.astype(np.float32), G.astype(np.float32)
+
+
+@pytest.mark.parametrize("M,hb,dt,sample", [((51,), 0.1, "f64", 0), ((12, 12), 0.2, "f32", 0),
+                                            ((6, 6, 6), 0.45, "f32", 0), ((32, 32), 0.08, "f32", 3000),
+                                            ((11, 14), 0.25, "f32", 0)])
+def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample):
+    _say(f"smooth_cov M={M} h={hb} {dt} sample={sample}")
+    rng = np.random.default_rng(300 + sum(M))
+    d = len(M)
+    P = int(np.prod(M))
+    if P <= 300:
+        C, G = _cov_inputs(rng, M, d)
+    else:
+        C = (rng.random((P, P)) + 0.01)
+        C = (C + C.T) * 0.5
+        G = C * rng.standard_normal((P, P))
+        G = (G + G.T) * 0.5
+    npdt = np.float64 if dt == "f64" else np.float32
+    C, G = C.astype(npdt), G.astype(npdt)
+    mu = rng.standard_normal(P).astype(npdt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    gam = torch.empty(P, P, dtype=tdt, device="cuda:0")
+    st = torch.empty(P, P, dtype=torch.int8, device="cuda:0")
+    F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F64 if dt == "f64" else F.FPCA_F32, dev(torch, C), dev(torch, G),
+                      dev(torch, mu), F.FPCA_K_EPANECHNIKOV, hb, gam, st)
+    h.sync()
+    gam_h, st_h = host(gam), host(st)
+    tol = 1e-10 if dt == "f64" else 1e-5
+    if sample == 0:
+        rb, rst = oracle.smooth_cov_raw(M, hb, C.astype(np.float64), G.astype(np.float64))
+        ref = oracle.assemble_cov(rb.reshape(P, P), mu.astype(np.float64))
+        assert status_agreement(st_h, rst)[0] == 0
+        okm = (rst.reshape(P, P) == 0) & (rst.reshape(P, P).T == 0)
+        assert normwise_rel(gam_h, ref, okm) < tol
+    else:
+        # sampled nodes (pairs (p,q) and (q,p) both evaluated) incl. the corners
+        idx = rng.integers(0, P * P, sample)
+        idx[:4] = [0, P - 1, (P - 1) * P, P * P - 1]
+        p, q = idx // P, idx % P
+        nodes = np.concatenate([idx, q * P + p])
+        rb, rst = oracle.smooth_cov_raw(M, hb, C.astype(np.float64), G.astype(np.float64), nodes)
+        m = len(idx)
+        ref = 0.5 * (rb[:m] + rb[m:]) - mu[p].astype(np.float64) * mu[q]
+        ok = (rst[:m] == 0) & (rst[m:] == 0)
+        assert normwise_rel(gam_h[p, q], ref, ok) < tol
+        assert status_agreement(st_h.reshape(-1)[nodes], rst)[0] == 0
+    assert np.array_equal(gam_h, gam_h.T)
+
+
+def test_smooth_cov_analytic_common_grid(torch, F, h):
+    """C = NULL (complete common-grid design) equals passing C = 1 - delta."""
+    _say("smooth_cov analytic C")
+    rng = np.random.default_rng(11)
+    M = (10, 10)
+    P = 100
+    G = rng.standard_normal((P, P))
+    G = ((G + G.T) / 2).astype(np.float32)
+    np.fill_diagonal(G, 0)
+    C = np.ones((P, P), np.float32)
+    np.fill_diagonal(C, 0)
+    outs = []
+    for Cin in (None, dev(torch, C)):
+        gam = torch.empty(P, P, dtype=torch.float32, device="cuda:0")
+        F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F32, Cin, dev(torch, G), None, F.FPCA_K_EPANECHNIKOV, 0.3, gam)
+        outs.append(host(gam))
+    h.sync()
+    rb, rst = oracle.smooth_cov_raw(M, 0.3, C.astype(np.float64), G.astype(np.float64))
+    ref = oracle.assemble_cov(rb.reshape(P, P), np.zeros(P))
+    for o in outs:
+        assert normwise_rel(o, ref) < 1e-5
+
+
+# ------------------------------------------------------------------ eigen
+def test_eig_closed_form_and_oracle(torch, F, h):
+    _say("eig closed form")
+    M = (24, 20)
+    P = 480
+    index = [(1, 1), (1, 2), (2, 1), (2, 2), (1, 3), (3, 1)]
+    lam = 2.0 ** -np.arange(1, 7)
+    pts = grid_points(M)
+    Phi = np.stack([fourier_1d(a, pts[:, 0]) * fourier_1d(b, pts[:, 1]) for a, b in index], 1)
+    Gam = (Phi * lam) @ Phi.T
+    rng = np.random.default_rng(3)
+    E = rng.standard_normal((P, P)) * 1e-4
+    Gam = Gam + (E + E.T) / 2
+    om = oracle.quad_weights(M, rule="trapezoid")
+    k, p, q, seed = 6, 10, 2, 7
+    for dt in ("f64", "f32"):
+        npdt = np.float64 if dt == "f64" else np.float32
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        ef = torch.empty(k, P, dtype=tdt, device="cuda:0")
+        ev, fve = F.fpca_eig_randomized(h, F.FPCA_F64 if dt == "f64" else F.FPCA_F32,
+                                        F.FPCA_PREC_F64 if dt == "f64" else F.FPCA_PREC_F32, F.Grid(M),
+                                        dev(torch, Gam.astype(npdt)), dev(torch, om), k, p, q, seed, ef)
+        rev, rphi, rfve = oracle.eig_randomized(Gam.astype(npdt).astype(np.float64), om, k, p, q, seed)
+        tol = 1e-10 if dt == "f64" else 1e-5
+        assert np.abs(ev - rev).max() <= tol * np.abs(rev).max()
+        assert np.abs(fve - rfve).max() <= tol
+        phi = host(ef).T
+        for j in range(k):
+            err = min(np.abs(phi[:, j] - rphi[:, j]).max(), np.abs(phi[:, j] + rphi[:, j]).max())
+            assert err <= 100 * tol * np.abs(rphi[:, j]).max(), (dt, j, err)
+        np.testing.assert_allclose(ev, lam, rtol=2e-3)
+
+
+def test_eig_riemann_default_weights_and_mask(torch, F, h):
+    _say("eig default weights")
+    M = (8, 8, 8)
+    P = 512
+    mask = disk_time_mask(M)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((P, 5))
+    Gam = X @ np.diag([5, 4, 3, 2, 1.0]) @ X.T
+    Gam[mask == 0, :] = 0
+    Gam[:, mask == 0] = 0
+    om = oracle.quad_weights(M, mask)
+    ef = torch.empty(4, P, dtype=torch.float32, device="cuda:0")
+    ev, fve = F.fpca_eig_randomized(h, F.FPCA_F32, F.FPCA_PREC_F32, F.Grid(M, dev(torch, mask)),
+                                    dev(torch, Gam.astype(np.float32)), None, 4, 6, 1, 9, ef)
+    rev, rphi, rfve = oracle.eig_dense(Gam.astype(np.float32).astype(np.float64), om, 4)
+    assert np.abs(ev - rev).max() <= 1e-5 * rev.max()
+    phi = host(ef).T
+    for j in range(4):
+        assert np.abs(phi[:, j] - rphi[:, j]).max() <= 1e-3 * np.abs(rphi[:, j]).max()
+    assert np.all(phi[mask == 0] == 0)
+
+
+# ------------------------------------------------------------------ end to end
+def test_end_to_end_c1(torch, F, h):
+    """d=1 FP64 workload, whole path, against the oracle's whole path."""
+    _say("end-to-end c1")
+    from paper_1510_04439_amd import pipeline as PL
+    ds = make_c1()
+    dd = PL.to_device(ds)
+    bufs = PL.alloc(dd, ds.k)
+    PL.fit(h, dd, bufs, ds.h_mean, ds.h_cov, ds.k, ds.oversample, ds.power_iters, ds.rp_seed)
+    h.sync()
+    c, s, _, _ = oracle.bin_mean(ds.M_mean, ds.offsets, ds.t, ds.y)
+    mu, mst = oracle.smooth_mean(ds.M_mean, ds.h_mean, c, s)
+    assert normwise_rel(host(bufs.mu), mu) < 1e-12
+    C, G = oracle.bin_cov_pairs(ds.M_cov, ds.offsets, ds.t, ds.y)
+    assert normwise_rel(host(bufs.G), G) < 1e-12
+    gh, gst = oracle.smooth_cov_raw(ds.M_cov, ds.h_cov, C, G)
+    gam = oracle.assemble_cov(gh.reshape(51, 51), mu[::2])
+    assert normwise_rel(host(bufs.gamma), gam) < 1e-11
+    om = oracle.quad_weights(ds.M_cov)
+    ev, phi, fve = oracle.eig_randomized(gam, om, ds.k, ds.oversample, ds.power_iters, ds.rp_seed)
+    assert np.abs(bufs.evals - ev).max() < 1e-10 * ev.max()
+    for j in range(ds.k):
+        assert np.abs(host(bufs.efuns)[j] - phi[:, j]).max() < 1e-8
+    # statistical sanity against the generating model (not parity)
+    np.testing.assert_allclose(bufs.evals, ds.lambdas, rtol=0.35)
