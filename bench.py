@@ -102,8 +102,8 @@ def main():
         F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_COV, dd.design, dd.dtype, F.FPCA_PREC_F32, dd.n, None, None,
                    dd.y, None, 0, bufs.extra.setdefault("Cs", torch.empty_like(bufs.G)), bufs.G)
         if ev: ev[2].record(stream)
-        F.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, None, bufs.G, bufs.mu, F.FPCA_K_EPANECHNIKOV, ds.h_cov,
-                          bufs.gamma, bufs.status)
+        F.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, None, PL.uniform_pair_weight(dd), bufs.G, bufs.mu,
+                          F.FPCA_K_EPANECHNIKOV, ds.h_cov, bufs.gamma, bufs.status)
         if ev: ev[3].record(stream)
         bufs.evals, bufs.fve = F.fpca_eig_randomized(h, dd.dtype, F.FPCA_PREC_F32, dd.grid_cov, bufs.gamma,
                                                      None, ds.k, ds.oversample, ds.power_iters, ds.rp_seed,

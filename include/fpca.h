@@ -156,17 +156,19 @@ int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const
  * products G from fpca_bin kind COV (slab 0), giving b0(s,t), then
  *   gamma[p,q] = (b0(p,q) + b0(q,p))/2 - mu[p] mu[q],
  * and gamma = 0 where node p or q lies outside the grid's mask (Section 3.1).
- *   C: P x P pair weights, or NULL for a complete common-grid design, where the
- *      weights are uniform off the diagonal and 0 on it (their scale does not
- *      change b0).
+ *   C: P x P pair weights, or NULL for a complete common-grid design, whose
+ *      pair weights are c_uniform off the diagonal and 0 on it (c_uniform =
+ *      n/(P(P-1)) for n curves observed at all P nodes, matching fpca_bin).
+ *   c_uniform: the off-diagonal pair weight used when C is NULL (> 0);
+ *      ignored otherwise.
  *   G: P x P raw products. mu: P values of the mean on this grid, or NULL to
  *      return the raw second-moment surface b0 (symmetrized) instead.
  *   bandwidth: host array of d bandwidths; the s- and t-coordinates share them.
  *   gamma: P x P output of `dtype`; status: optional P x P int8.
  */
 int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const void *C,
-                    const void *G, const void *mu, int kernel, const double *bandwidth,
-                    void *gamma, int8_t *status);
+                    double c_uniform, const void *G, const void *mu, int kernel,
+                    const double *bandwidth, void *gamma, int8_t *status);
 
 /*
  * fpca_eig_randomized -- top-k eigenpairs of the matrixized covariance

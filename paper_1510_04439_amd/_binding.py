@@ -65,7 +65,7 @@ def load_library(path: str = LIB_PATH):
                            vp, vp, vp, vp, vp]
     L.fpca_smooth_mean.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), vp, vp]
-    L.fpca_smooth_cov.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, i32,
+    L.fpca_smooth_cov.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, ctypes.c_double, vp, vp, i32,
                                   ctypes.POINTER(ctypes.c_double), vp, vp]
     L.fpca_eig_randomized.argtypes = [vp, i32, i32, ctypes.POINTER(_GridC), vp, vp, i32, i32, i32, u64,
                                       ctypes.POINTER(ctypes.c_double), vp,
@@ -163,10 +163,11 @@ def fpca_smooth_mean(h: Handle, grid: Grid, dtype: int, weights, sums, kernel: i
                                            kernel, _bw(bandwidth, grid.d), _ptr(mu), _ptr(status)))
 
 
-def fpca_smooth_cov(h: Handle, grid: Grid, dtype: int, C, G, mu, kernel: int, bandwidth, gamma,
-                    status=None):
+def fpca_smooth_cov(h: Handle, grid: Grid, dtype: int, C, c_uniform: float, G, mu, kernel: int, bandwidth,
+                    gamma, status=None):
     g = grid.c()
-    _check(load_library().fpca_smooth_cov(h.ptr, ctypes.byref(g), dtype, _ptr(C), _ptr(G), _ptr(mu),
+    _check(load_library().fpca_smooth_cov(h.ptr, ctypes.byref(g), dtype, _ptr(C), float(c_uniform), _ptr(G),
+                                          _ptr(mu),
                                           kernel, _bw(bandwidth, grid.d), _ptr(gamma), _ptr(status)))
 
 

@@ -12,11 +12,12 @@
 #include <vector>
 
 #include "common.hpp"
+#include "wls.hpp"
 
 namespace fpca {
 
-int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, const float *G,
-                        const double *bw, float *raw, int8_t *status, bool analytic_C);
+int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, double c0, const float *G,
+                        const double *bw, const float *mu, float *gamma, int8_t *status);
 bool smooth_cov_fused_d2_supported(const fpca_grid *grid, const double *bw);
 
 namespace {
@@ -61,93 +62,6 @@ struct MomPtrs {
 };
 
 }  // namespace
-
-// Solve [[S0, S1^T], [S1, S2]] beta = [T0; T1] in FP64 for b0 = beta_0.
-// Status: EMPTY if S0 <= 0 (b0 = NaN); FALLBACK (b0 = T0/S0) if a diagonal
-// entry is not positive or the Cholesky factorization of the Jacobi-scaled
-// (unit-diagonal) matrix meets a pivot that is not positive or below 1e-10;
-// OK otherwise. `m` holds the moments in the order S0, S1[D], S2 (upper
-// triangle, row by row), T0, T1[D].
-template <int D>
-__device__ inline double wls_b0(const double *m, int8_t *st) {
-  constexpr int n = D + 1;
-  double A[n][n], r[n], sc[n];
-  const double S0 = m[0];
-  const double T0 = m[1 + D + D * (D + 1) / 2];
-  if (!(S0 > 0.0)) {
-    *st = FPCA_STATUS_EMPTY;
-    return __builtin_nan("");
-  }
-  A[0][0] = S0;
-  r[0] = T0;
-  int q = 1 + D;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    A[0][1 + k] = A[1 + k][0] = m[1 + k];
-    r[1 + k] = m[2 + D + D * (D + 1) / 2 + k];
-  }
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-#pragma unroll
-    for (int l = k; l < D; ++l) {
-      A[1 + k][1 + l] = A[1 + l][1 + k] = m[q++];
-    }
-  const double fb = T0 / S0;
-#pragma unroll
-  for (int i = 0; i < n; ++i) {
-    if (!(A[i][i] > 0.0)) {
-      *st = FPCA_STATUS_FALLBACK;
-      return fb;
-    }
-    sc[i] = 1.0 / sqrt(A[i][i]);
-  }
-#pragma unroll
-  for (int i = 0; i < n; ++i) {
-    r[i] *= sc[i];
-#pragma unroll
-    for (int j = 0; j < n; ++j) A[i][j] *= sc[i] * sc[j];
-  }
-  // In-place Cholesky: lower triangle of A becomes L.
-#pragma unroll
-  for (int j = 0; j < n; ++j) {
-    double dj = A[j][j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) dj -= A[j][k] * A[j][k];
-    if (!(dj >= 1e-10)) {
-      *st = FPCA_STATUS_FALLBACK;
-      return fb;
-    }
-    const double ljj = sqrt(dj);
-    A[j][j] = ljj;
-    const double inv = 1.0 / ljj;
-#pragma unroll
-    for (int i = j + 1; i < n; ++i) {
-      double v = A[i][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
-      A[i][j] = v * inv;
-    }
-  }
-  double z[n];
-#pragma unroll
-  for (int i = 0; i < n; ++i) {
-    double v = r[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) v -= A[i][k] * z[k];
-    z[i] = v / A[i][i];
-  }
-  double x0 = 0.0;
-#pragma unroll
-  for (int i = n - 1; i >= 0; --i) {
-    double v = z[i];
-#pragma unroll
-    for (int k = i + 1; k < n; ++k) v -= A[k][i] * r[k];
-    r[i] = v / A[i][i];  // reuse r as the solution
-    if (i == 0) x0 = r[0];
-  }
-  *st = FPCA_STATUS_OK;
-  return x0 * sc[0];
-}
 
 namespace {
 
@@ -207,10 +121,10 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t P, T *__restrict__ A, 
 }
 
 template <typename T>
-__global__ void k_offdiag_ones(T *A, int64_t P) {
+__global__ void k_offdiag_fill(T *A, int64_t P, T v) {
   int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int64_t step = int64_t(gridDim.x) * blockDim.x;
-  for (; e < P * P; e += step) A[e] = (e / P == e % P) ? T(0) : T(1);
+  for (; e < P * P; e += step) A[e] = (e / P == e % P) ? T(0) : v;
 }
 
 inline unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
@@ -373,41 +287,34 @@ int assemble(fpca_context *ctx, int64_t P, T *A, const T *mu, const uint8_t *mas
 }
 
 template <typename T>
-int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, const T *G, const T *mu,
-                    const double *bw, T *gamma, int8_t *status) {
+int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double c_uniform, const T *G,
+                    const T *mu, const double *bw, T *gamma, int8_t *status) {
   const GridDims gd = make_dims(grid);
   const int64_t P = gd.P;
   const int d = grid->d;
-  bool done = false;
   if constexpr (sizeof(T) == 4) {
-    if (d == 2 && smooth_cov_fused_d2_supported(grid, bw)) {
-      if (int rc = smooth_cov_fused_d2(ctx, grid, C, G, bw, gamma, status, C == nullptr)) return rc;
-      done = true;
-    }
+    if (d == 2 && smooth_cov_fused_d2_supported(grid, bw))
+      return smooth_cov_fused_d2(ctx, grid, C, c_uniform, G, bw, mu, gamma, status);
   }
-  if (!done) {
-    int dims[MAXD];
-    double h[MAXD];
-    for (int k = 0; k < d; ++k) {
-      dims[k] = dims[k + d] = grid->M[k];
-      h[k] = h[k + d] = bw[k];
-    }
-    const T *Cuse = C;
-    if (!C) {
-      // complete common grid: uniform pair weights off the diagonal; kept in
-      // the output buffer's place until the smoother has read it
-      if (int rc = ws_reserve(ctx, 0)) return rc;
-      T *tmp = nullptr;
-      FPCA_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), sizeof(T) * P * P, ctx->stream));
-      hipLaunchKernelGGL(k_offdiag_ones<T>, dim3(nblk(P * P) > 65536 ? 65536 : nblk(P * P)), dim3(256), 0,
-                         ctx->stream, tmp, P);
-      FPCA_LAUNCH_CHECK("offdiag");
-      int rc = smooth_generic<T>(ctx, 2 * d, dims, h, tmp, G, gamma, status);
-      (void)hipFreeAsync(tmp, ctx->stream);
-      if (rc) return rc;
-    } else {
-      if (int rc = smooth_generic<T>(ctx, 2 * d, dims, h, Cuse, G, gamma, status)) return rc;
-    }
+  int dims[MAXD];
+  double h[MAXD];
+  for (int k = 0; k < d; ++k) {
+    dims[k] = dims[k + d] = grid->M[k];
+    h[k] = h[k + d] = bw[k];
+  }
+  if (!C) {
+    // complete common grid: the pair weights c_uniform (1 - delta_pq) are
+    // materialized for the general engine
+    T *tmp = nullptr;
+    FPCA_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), sizeof(T) * P * P, ctx->stream));
+    hipLaunchKernelGGL(k_offdiag_fill<T>, dim3(nblk(P * P) > 65536 ? 65536 : nblk(P * P)), dim3(256), 0,
+                       ctx->stream, tmp, P, T(c_uniform));
+    FPCA_LAUNCH_CHECK("offdiag");
+    int rc = smooth_generic<T>(ctx, 2 * d, dims, h, tmp, G, gamma, status);
+    (void)hipFreeAsync(tmp, ctx->stream);
+    if (rc) return rc;
+  } else {
+    if (int rc = smooth_generic<T>(ctx, 2 * d, dims, h, C, G, gamma, status)) return rc;
   }
   return assemble<T>(ctx, P, gamma, mu, grid->mask);
 }
@@ -434,20 +341,24 @@ extern "C" int fpca_smooth_mean(fpca_handle ctx, const fpca_grid *grid, int dtyp
                                static_cast<const float *>(sums), static_cast<float *>(mu), status);
 }
 
-extern "C" int fpca_smooth_cov(fpca_handle ctx, const fpca_grid *grid, int dtype, const void *C, const void *G,
-                               const void *mu, int kernel, const double *bandwidth, void *gamma, int8_t *status) {
+extern "C" int fpca_smooth_cov(fpca_handle ctx, const fpca_grid *grid, int dtype, const void *C, double c_uniform,
+                               const void *G, const void *mu, int kernel, const double *bandwidth, void *gamma,
+                               int8_t *status) {
   if (int rc = check_handle(ctx)) return rc;
   int64_t P;
   if (int rc = check_grid(grid, &P)) return rc;
   if (kernel != FPCA_K_EPANECHNIKOV) return set_error(FPCA_ERR_UNSUPPORTED, "kernel %d", kernel);
   if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype %d", dtype);
   if (!G || !gamma) return set_error(FPCA_ERR_INVALID_ARG, "G and gamma are required");
+  if (!C && !(c_uniform > 0.0 && std::isfinite(c_uniform)))
+    return set_error(FPCA_ERR_INVALID_ARG, "C = NULL needs a positive c_uniform");
   if (P > (int64_t(1) << 15)) return set_error(FPCA_ERR_UNSUPPORTED, "covariance grid too large (P=%lld)", (long long)P);
   if (int rc = check_bw(bandwidth, grid->d)) return rc;
   if (int rc = set_device(ctx)) return rc;
   if (dtype == FPCA_F64)
-    return smooth_cov_impl<double>(ctx, grid, static_cast<const double *>(C), static_cast<const double *>(G),
-                                   static_cast<const double *>(mu), bandwidth, static_cast<double *>(gamma), status);
-  return smooth_cov_impl<float>(ctx, grid, static_cast<const float *>(C), static_cast<const float *>(G),
+    return smooth_cov_impl<double>(ctx, grid, static_cast<const double *>(C), c_uniform,
+                                   static_cast<const double *>(G), static_cast<const double *>(mu), bandwidth,
+                                   static_cast<double *>(gamma), status);
+  return smooth_cov_impl<float>(ctx, grid, static_cast<const float *>(C), c_uniform, static_cast<const float *>(G),
                                 static_cast<const float *>(mu), bandwidth, static_cast<float *>(gamma), status);
 }

@@ -1,10 +1,464 @@
-// Fused covariance smoother for d = 2 (placeholder until the fused kernels land).
+// Fused covariance smoother for d = 2 (eq. 2.4 on the 4-dimensional grid of
+// (s1, s2, t1, t2)), in two kernels:
+//
+//  stage T: one workgroup per s-row of C and G (a whole t-plane, held in LDS):
+//           the t2 and t1 passes produce the partial moments in t,
+//           G: (t-exponents) 00, 10, 01;  C: 00, 10, 01, 20, 11, 02.
+//  stage S: a workgroup owns 8 consecutive t columns, one wavefront per
+//           column, lane = s2. It streams the s1 rows of the partial moments
+//           (staged through LDS for coalescing), keeps a register window of
+//           2R+1 rows for the s1 pass, does the s2 pass with DPP wave shifts,
+//           and solves the 5x5 FP64 system per lane. Only nodes p <= q are
+//           computed (the surface is symmetric); each is written at (p,q)
+//           and (q,p) with mu(p)mu(q) subtracted and the domain mask applied.
+//
+// When C is the complete common-grid pair weight c0 (1 - delta_pq), the 15
+// weight moments are exact products of 1-D tap sums minus the diagonal part,
+// evaluated in FP64 from small tables; only G is convolved.
+#include <cmath>
+
 #include "common.hpp"
+#include "wls.hpp"
 
 namespace fpca {
-bool smooth_cov_fused_d2_supported(const fpca_grid *, const double *) { return false; }
-int smooth_cov_fused_d2(fpca_context *, const fpca_grid *, const float *, const float *, const double *, float *,
-                        int8_t *, bool) {
-  return set_error(FPCA_ERR_UNSUPPORTED, "fused d=2 smoother not built");
+
+namespace {
+
+constexpr int RMAX = 8;
+constexpr int TW = 8;  // t columns per stage-S workgroup (one per wavefront)
+
+struct Taps {
+  float k[3][2 * RMAX + 1];  // (1-u^2)u^j at offsets -R..R
+};
+
+// Analytic weight-moment tables (FP64), per coordinate k = 0, 1 of the d = 2 grid:
+//   W[k][e][x]      = sum over the window at x of (1-u^2) u^e           (e = 0,1,2)
+//   Dg[k][ab][i][j] = sum_y (1-u_i^2) u_i^a (1-u_j^2) u_j^b, u_i = (y-i)/H
+// with ab over (0,0),(1,0),(0,1),(2,0),(1,1),(0,2).
+struct TabPtrs {
+  const double *W;   // [2][3][Mmax]
+  const double *Dg;  // [2][6][Mmax][Mmax]
+  int Mmax;
+};
+
+__device__ inline int ab_index(int a, int b) {
+  // (0,0)0 (1,0)1 (0,1)2 (2,0)3 (1,1)4 (0,2)5
+  if (a == 0 && b == 0) return 0;
+  if (a == 1 && b == 0) return 1;
+  if (a == 0 && b == 1) return 2;
+  if (a == 2) return 3;
+  if (a == 1) return 4;
+  return 5;
 }
+
+__global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, int Mmax, double *W, double *Dg) {
+  const int k = blockIdx.y;
+  const int M = k == 0 ? M0 : M1;
+  const double H = k == 0 ? H0 : H1;
+  const int R = k == 0 ? R0 : R1;
+  const int64_t nW = 3 * int64_t(Mmax), nD = 6 * int64_t(Mmax) * Mmax;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nW + nD; e += int64_t(gridDim.x) * blockDim.x) {
+    if (e < nW) {
+      const int ex = int(e / Mmax), x = int(e % Mmax);
+      double s = 0.0;
+      if (x < M)
+        for (int m = -R; m <= R; ++m) {
+          if (x + m < 0 || x + m >= M) continue;
+          const double u = double(m) / H;
+          const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
+          s += K * (ex == 0 ? 1.0 : (ex == 1 ? u : u * u));
+        }
+      W[int64_t(k) * nW + e] = s;
+    } else {
+      const int64_t f = e - nW;
+      const int ab = int(f / (int64_t(Mmax) * Mmax));
+      const int i = int((f / Mmax) % Mmax), j = int(f % Mmax);
+      const int a = (ab == 1 || ab == 4) ? 1 : (ab == 3 ? 2 : 0);
+      const int b = (ab == 2 || ab == 4) ? 1 : (ab == 5 ? 2 : 0);
+      double s = 0.0;
+      if (i < M && j < M)
+        for (int y = 0; y < M; ++y) {
+          const double ui = double(y - i) / H, uj = double(y - j) / H;
+          const double Ki = fabs(ui) < 1.0 ? 1.0 - ui * ui : 0.0;
+          const double Kj = fabs(uj) < 1.0 ? 1.0 - uj * uj : 0.0;
+          if (Ki == 0.0 || Kj == 0.0) continue;
+          s += Ki * (a == 0 ? 1.0 : (a == 1 ? ui : ui * ui)) * Kj * (b == 0 ? 1.0 : (b == 1 ? uj : uj * uj));
+        }
+      Dg[int64_t(k) * nD + f] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- stage T
+// U layout: NU arrays of P x P (row s, column t). Array order:
+//   0 G00, 1 G10, 2 G01, [3 C00, 4 C10, 5 C01, 6 C20, 7 C11, 8 C02]
+// (exponents of u in (t1, t2)).
+template <bool ANALYTIC>
+__global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, const float *__restrict__ C,
+                                                  const float *__restrict__ G, Taps tp, int R,
+                                                  float *__restrict__ U) {
+  constexpr int NA = ANALYTIC ? 2 : 5;  // t2-pass arrays: GK GU [CK CU CUU]
+  extern __shared__ float lds[];
+  float *rowG = lds;                  // P
+  float *rowC = lds + P;              // P (general only)
+  float *A = lds + (ANALYTIC ? 1 : 2) * P;  // NA x P
+  const int64_t s = blockIdx.x;
+  const float *g = G + s * P;
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
+    rowG[e] = g[e];
+    if (!ANALYTIC) rowC[e] = C[s * P + e];
+  }
+  __syncthreads();
+  // t2 pass (contiguous coordinate)
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
+    const int t1 = int(e / M2), t2 = int(e % M2);
+    const int lo = -min(R, t2), hi = min(R, M2 - 1 - t2);
+    float gk = 0.f, gu = 0.f, ck = 0.f, cu = 0.f, cuu = 0.f;
+    for (int m = lo; m <= hi; ++m) {
+      const float k0 = tp.k[0][m + R], k1 = tp.k[1][m + R];
+      const float vg = rowG[e + m];
+      gk = fmaf(k0, vg, gk);
+      gu = fmaf(k1, vg, gu);
+      if (!ANALYTIC) {
+        const float vc = rowC[e + m];
+        ck = fmaf(k0, vc, ck);
+        cu = fmaf(k1, vc, cu);
+        cuu = fmaf(tp.k[2][m + R], vc, cuu);
+      }
+    }
+    (void)t1;
+    A[0 * P + e] = gk;
+    A[1 * P + e] = gu;
+    if (!ANALYTIC) {
+      A[2 * P + e] = ck;
+      A[3 * P + e] = cu;
+      A[4 * P + e] = cuu;
+    }
+  }
+  __syncthreads();
+  // t1 pass (stride M2), written to HBM row s
+  const int64_t PP = P * P;
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
+    const int t1 = int(e / M2);
+    const int lo = -min(R, t1), hi = min(R, M1 - 1 - t1);
+    float g00 = 0.f, g10 = 0.f, g01 = 0.f;
+    float c00 = 0.f, c10 = 0.f, c20 = 0.f, c01 = 0.f, c11 = 0.f, c02 = 0.f;
+    for (int m = lo; m <= hi; ++m) {
+      const float k0 = tp.k[0][m + R], k1 = tp.k[1][m + R];
+      const int64_t o = e + int64_t(m) * M2;
+      const float gk = A[0 * P + o], gu = A[1 * P + o];
+      g00 = fmaf(k0, gk, g00);
+      g10 = fmaf(k1, gk, g10);
+      g01 = fmaf(k0, gu, g01);
+      if (!ANALYTIC) {
+        const float ck = A[2 * P + o], cu = A[3 * P + o], cuu = A[4 * P + o];
+        c00 = fmaf(k0, ck, c00);
+        c10 = fmaf(k1, ck, c10);
+        c20 = fmaf(tp.k[2][m + R], ck, c20);
+        c01 = fmaf(k0, cu, c01);
+        c11 = fmaf(k1, cu, c11);
+        c02 = fmaf(k0, cuu, c02);
+      }
+    }
+    float *u = U + s * P + e;
+    u[0 * PP] = g00;
+    u[1 * PP] = g10;
+    u[2 * PP] = g01;
+    if (!ANALYTIC) {
+      u[3 * PP] = c00;
+      u[4 * PP] = c10;
+      u[5 * PP] = c01;
+      u[6 * PP] = c20;
+      u[7 * PP] = c11;
+      u[8 * PP] = c02;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- stage S
+// Lane l receives lane l+1's value (wave_shl:1); lane 63 receives 0.
+__device__ inline float from_next(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, true));
+}
+// Lane l receives lane l-1's value (wave_shr:1); lane 0 receives 0.
+__device__ inline float from_prev(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, true));
+}
+
+// out_j = sum_m tap_j[m] x(lane + m), m = -R..R, for NJ tap rows j.
+template <int R, int NJ>
+__device__ inline void lane_conv(float x, const Taps &tp, float *out) {
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) out[j] = tp.k[j][R] * x;
+  float up = x, dn = x;
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    up = from_next(up);  // x(lane + m)
+    dn = from_prev(dn);  // x(lane - m)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      out[j] = fmaf(tp.k[j][R + m], up, out[j]);
+      out[j] = fmaf(tp.k[j][R - m], dn, out[j]);
+    }
+  }
+}
+
+// s1-window of one array: sum_m tap_j[m] win[R+m]
+template <int R, int J>
+__device__ inline float win_conv(const float *win, const Taps &tp) {
+  float a = 0.f;
+#pragma unroll
+  for (int i = 0; i <= 2 * R; ++i) a = fmaf(tp.k[J][i], win[i], a);
+  return a;
+}
+
+template <bool ANALYTIC, int R>
+__global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, const float *__restrict__ U, Taps tp,
+                                                  const float *__restrict__ mu, const uint8_t *__restrict__ mask,
+                                                  double c0, TabPtrs tab, int nchunks, float *__restrict__ gamma,
+                                                  int8_t *__restrict__ status) {
+  constexpr int NU = ANALYTIC ? 3 : 9;
+  constexpr int W = 2 * R + 1;
+  __shared__ float stage[2][NU][64][TW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Chunk order: the chunks sharing a 128-byte line of a row (4 chunks of 8
+  // floats) land on one XCD (dispatch is round-robin over 8 XCDs), and the
+  // chunks with the most work (largest t1) come first.
+  int chunk;
+  {
+    const int b = blockIdx.x;
+    const int nlines = (nchunks + 3) / 4;
+    const int L = (b / 32) * 8 + (b % 8);
+    const int sib = (b / 8) % 4;
+    int line = nlines - 1 - L;
+    chunk = line * 4 + sib;
+    if (L >= nlines || chunk >= nchunks || chunk < 0) chunk = -1;
+  }
+  if (chunk < 0) return;  // uniform across the workgroup
+  const int64_t t0 = int64_t(chunk) * TW;
+  const int64_t t = t0 + wave;
+  const bool wave_ok = t < P;
+  const int t1 = wave_ok ? int(t / M2) : -1;
+  const int t2 = wave_ok ? int(t % M2) : 0;
+  // last output row of any wave in this workgroup
+  int xmax = int(min(int64_t(P - 1), t0 + TW - 1) / M2);
+  const int64_t PP = P * P;
+
+  // static per-lane factors of the analytic weight moments
+  double Af[15], Bf[15];
+  if (ANALYTIC) {
+    const int Mm = tab.Mmax;
+    const double *W1 = tab.W, *W2 = tab.W + 3 * Mm;
+    const double *D2 = tab.Dg + 6 * int64_t(Mm) * Mm;
+    const int s2 = lane < M2 ? lane : 0;
+    // e = (a1, a2, b1, b2) in moment order
+    const int E[15][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
+                          {2, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {1, 0, 0, 1}, {0, 2, 0, 0},
+                          {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 2, 0}, {0, 0, 1, 1}, {0, 0, 0, 2}};
+#pragma unroll
+    for (int q = 0; q < 15; ++q) {
+      Af[q] = W2[E[q][1] * Mm + s2] * W1[E[q][2] * Mm + (t1 < 0 ? 0 : t1)] * W2[E[q][3] * Mm + t2];
+      Bf[q] = D2[(int64_t(ab_index(E[q][1], E[q][3])) * Mm + s2) * Mm + t2];
+    }
+  }
+
+  float win[NU][W];
+#pragma unroll
+  for (int a = 0; a < NU; ++a)
+#pragma unroll
+    for (int i = 0; i < W; ++i) win[a][i] = 0.f;
+
+  const int nload = NU * 64 * TW;
+  for (int r = 0; r <= xmax + R; ++r) {
+    const int buf = r & 1;
+    for (int e = tid; e < nload; e += 512) {
+      const int a = e / (64 * TW), rem = e % (64 * TW);
+      const int s2 = rem / TW, tt = rem % TW;
+      float v = 0.f;
+      if (r < M1 && s2 < M2 && t0 + tt < P) v = U[a * PP + (int64_t(r) * M2 + s2) * P + t0 + tt];
+      stage[buf][a][s2][tt] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+      for (int i = 0; i < W - 1; ++i) win[a][i] = win[a][i + 1];
+      win[a][W - 1] = stage[buf][a][lane][wave];
+    }
+    const int x = r - R;
+    if (x < 0 || !wave_ok || x > t1) continue;  // no output row for this wavefront
+    // s1 pass (exponent of u in s1 is the second index)
+    const float g00_0 = win_conv<R, 0>(win[0], tp), g00_1 = win_conv<R, 1>(win[0], tp);
+    const float g10_0 = win_conv<R, 0>(win[1], tp), g01_0 = win_conv<R, 0>(win[2], tp);
+    // s2 pass across lanes
+    double m[20];
+    {
+      float o2[2], o1[1];
+      lane_conv<R, 2>(g00_0, tp, o2);  // T0, T1_s2
+      const float T0 = o2[0], Ts2 = o2[1];
+      lane_conv<R, 1>(g00_1, tp, o1);
+      const float Ts1 = o1[0];
+      lane_conv<R, 1>(g10_0, tp, o1);
+      const float Tt1 = o1[0];
+      lane_conv<R, 1>(g01_0, tp, o1);
+      const float Tt2 = o1[0];
+      m[15] = T0;
+      m[16] = Ts1;
+      m[17] = Ts2;
+      m[18] = Tt1;
+      m[19] = Tt2;
+    }
+    if (ANALYTIC) {
+      const int Mm = tab.Mmax;
+      const double *W1 = tab.W;
+      const double *D1 = tab.Dg;
+      const double w0 = W1[0 * Mm + x], w1 = W1[1 * Mm + x], w2 = W1[2 * Mm + x];
+      const int tt1 = t1;
+      auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
+      const int E1[15][2] = {{0, 0}, {1, 0}, {0, 0}, {0, 1}, {0, 0}, {2, 0}, {1, 0}, {1, 1},
+                             {1, 0}, {0, 0}, {0, 1}, {0, 0}, {0, 2}, {0, 1}, {0, 0}};
+#pragma unroll
+      for (int q = 0; q < 15; ++q) {
+        const double wa = E1[q][0] == 0 ? w0 : (E1[q][0] == 1 ? w1 : w2);
+        m[q] = c0 * (wa * Af[q] - d1(E1[q][0], E1[q][1]) * Bf[q]);
+      }
+    } else {
+      const float c00_0 = win_conv<R, 0>(win[3], tp), c00_1 = win_conv<R, 1>(win[3], tp),
+                  c00_2 = win_conv<R, 2>(win[3], tp);
+      const float c10_0 = win_conv<R, 0>(win[4], tp), c10_1 = win_conv<R, 1>(win[4], tp);
+      const float c01_0 = win_conv<R, 0>(win[5], tp), c01_1 = win_conv<R, 1>(win[5], tp);
+      const float c20_0 = win_conv<R, 0>(win[6], tp), c11_0 = win_conv<R, 0>(win[7], tp),
+                  c02_0 = win_conv<R, 0>(win[8], tp);
+      float o3[3], o2[2], o1[1];
+      lane_conv<R, 3>(c00_0, tp, o3);
+      m[0] = o3[0];   // S0
+      m[2] = o3[1];   // S1 s2
+      m[9] = o3[2];   // S2 s2s2
+      lane_conv<R, 2>(c00_1, tp, o2);
+      m[1] = o2[0];   // S1 s1
+      m[6] = o2[1];   // S2 s1s2
+      lane_conv<R, 1>(c00_2, tp, o1);
+      m[5] = o1[0];   // S2 s1s1
+      lane_conv<R, 2>(c10_0, tp, o2);
+      m[3] = o2[0];   // S1 t1
+      m[10] = o2[1];  // S2 s2t1
+      lane_conv<R, 1>(c10_1, tp, o1);
+      m[7] = o1[0];   // S2 s1t1
+      lane_conv<R, 2>(c01_0, tp, o2);
+      m[4] = o2[0];   // S1 t2
+      m[11] = o2[1];  // S2 s2t2
+      lane_conv<R, 1>(c01_1, tp, o1);
+      m[8] = o1[0];   // S2 s1t2
+      lane_conv<R, 1>(c20_0, tp, o1);
+      m[12] = o1[0];  // S2 t1t1
+      lane_conv<R, 1>(c11_0, tp, o1);
+      m[13] = o1[0];  // S2 t1t2
+      lane_conv<R, 1>(c02_0, tp, o1);
+      m[14] = o1[0];  // S2 t2t2
+    }
+    if (lane >= M2) continue;
+    const int64_t p = int64_t(x) * M2 + lane;
+    if (p > t) continue;
+    int8_t st;
+    double b0 = wls_b0<4>(m, &st);
+    if (mu) b0 -= double(mu[p]) * double(mu[t]);
+    if (mask && (!mask[p] || !mask[t])) b0 = 0.0;
+    const float v = float(b0);
+    gamma[t * P + p] = v;
+    gamma[p * P + t] = v;
+    if (status) {
+      status[t * P + p] = st;
+      status[p * P + t] = st;
+    }
+  }
+}
+
+int tap_radius(double h, int M) { return int(std::floor(h * double(M - 1))); }
+
+}  // namespace
+
+bool smooth_cov_fused_d2_supported(const fpca_grid *grid, const double *bw) {
+  if (grid->d != 2) return false;
+  const int M1 = grid->M[0], M2 = grid->M[1];
+  if (M2 > 64 || int64_t(M1) * M2 > 4096) return false;
+  const int R1 = tap_radius(bw[0], M1), R2 = tap_radius(bw[1], M2);
+  if (R1 != R2 || R1 < 1 || R1 > RMAX) return false;
+  // the same taps serve both coordinates
+  if (std::fabs(bw[0] * (M1 - 1) - bw[1] * (M2 - 1)) > 1e-12 * bw[0] * (M1 - 1)) return false;
+  return true;
+}
+
+int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, double c0, const float *G,
+                        const double *bw, const float *mu, float *gamma, int8_t *status) {
+  const int M1 = grid->M[0], M2 = grid->M[1];
+  const int64_t P = int64_t(M1) * M2;
+  const int R = tap_radius(bw[0], M1);
+  const double H = bw[0] * double(M1 - 1);
+  const bool analytic = (C == nullptr);
+  Taps tp{};
+  for (int j = 0; j < 3; ++j)
+    for (int m = -R; m <= R; ++m) {
+      const double u = double(m) / H;
+      const double K = std::fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
+      tp.k[j][m + R] = float(K * (j == 0 ? 1.0 : (j == 1 ? u : u * u)));
+    }
+  const int NU = analytic ? 3 : 9;
+  const int Mmax = M1 > M2 ? M1 : M2;
+  const size_t bytesU = carve_bytes(size_t(NU) * P * P, 4);
+  const size_t bytesT = analytic ? carve_bytes(2 * 3 * Mmax, 8) + carve_bytes(2 * 6 * size_t(Mmax) * Mmax, 8) : 0;
+  if (int rc = ws_reserve(ctx, bytesU + bytesT)) return rc;
+  Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
+  float *U = cv.take<float>(size_t(NU) * P * P);
+  TabPtrs tab{nullptr, nullptr, Mmax};
+  if (analytic) {
+    double *Wt = cv.take<double>(2 * 3 * Mmax);
+    double *Dt = cv.take<double>(2 * 6 * size_t(Mmax) * Mmax);
+    const double H2 = bw[1] * double(M2 - 1);
+    hipLaunchKernelGGL(k_tables, dim3(64, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2),
+                       Mmax, Wt, Dt);
+    FPCA_LAUNCH_CHECK("tables");
+    tab.W = Wt;
+    tab.Dg = Dt;
+  }
+  const size_t lds_t = size_t((analytic ? 1 : 2) + (analytic ? 2 : 5)) * P * sizeof(float);
+  if (analytic) {
+    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));
+  } else {
+    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));
+  }
+  if (analytic)
+    hipLaunchKernelGGL(k_stage_t<true>, dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, tp, R, U);
+  else
+    hipLaunchKernelGGL(k_stage_t<false>, dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, tp, R, U);
+  FPCA_LAUNCH_CHECK("stage_t");
+  const int nchunks = int((P + TW - 1) / TW);
+  const int nlines = (nchunks + 3) / 4;
+  const int grid_s = ((nlines + 7) / 8) * 32;
+#define STAGE_S(A, RR)                                                                                      \
+  hipLaunchKernelGGL((k_stage_s<A, RR>), dim3(grid_s), dim3(512), 0, ctx->stream, M1, M2, P, U, tp, mu,     \
+                     grid->mask, c0, tab, nchunks, gamma, status)
+#define STAGE_S_R(A)          \
+  switch (R) {                \
+    case 1: STAGE_S(A, 1); break; \
+    case 2: STAGE_S(A, 2); break; \
+    case 3: STAGE_S(A, 3); break; \
+    case 4: STAGE_S(A, 4); break; \
+    case 5: STAGE_S(A, 5); break; \
+    case 6: STAGE_S(A, 6); break; \
+    case 7: STAGE_S(A, 7); break; \
+    default: STAGE_S(A, 8); break; \
+  }
+  if (analytic) {
+    STAGE_S_R(true)
+  } else {
+    STAGE_S_R(false)
+  }
+#undef STAGE_S_R
+#undef STAGE_S
+  FPCA_LAUNCH_CHECK("stage_s");
+  return FPCA_OK;
+}
+
 }  // namespace fpca

@@ -100,12 +100,20 @@ def fit(h: B.Handle, dd: DeviceData, bufs: FitBuffers, h_mean: float, h_cov: flo
         C = bufs.C
         B.fpca_bin(h, dd.grid_cov, B.FPCA_BIN_COV, dd.design, dd.dtype, prec, dd.n, dd.offsets, dd.t,
                    dd.y, None, 0, C, bufs.G)
-    B.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, C, bufs.G, mu_cov, B.FPCA_K_EPANECHNIKOV, h_cov,
-                      bufs.gamma, bufs.status)
+    B.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, C, uniform_pair_weight(dd), bufs.G, mu_cov,
+                      B.FPCA_K_EPANECHNIKOV, h_cov, bufs.gamma, bufs.status)
     if do_eig:
         bufs.evals, bufs.fve = B.fpca_eig_randomized(h, dd.dtype, eig_prec, dd.grid_cov, bufs.gamma, None,
                                                      k, oversample, power_iters, seed, bufs.efuns)
     return bufs
+
+
+def uniform_pair_weight(dd: DeviceData) -> float:
+    """Pair weight n/(P(P-1)) of a complete common-grid design (0 otherwise)."""
+    if dd.design != B.FPCA_COMMON_GRID:
+        return 0.0
+    P = dd.grid_cov.P
+    return dd.n / (P * (P - 1.0))
 
 
 def mean_on_cov_grid(dd: DeviceData, bufs: FitBuffers):

@@ -9,6 +9,8 @@ def normwise_rel(x, ref, mask=None):
     if mask is not None:
         m = np.asarray(mask).reshape(-1).astype(bool)
         x, ref = x[m], ref[m]
+    if ref.size == 0:
+        return 0.0
     den = np.abs(ref).max()
     return float(np.abs(x - ref).max() / (den if den > 0 else 1.0))
 

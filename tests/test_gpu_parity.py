@@ -212,7 +212,8 @@ def _cov_inputs(rng, M, d):
 
 @pytest.mark.parametrize("M,hb,dt,sample", [((51,), 0.1, "f64", 0), ((12, 12), 0.2, "f32", 0),
                                             ((6, 6, 6), 0.45, "f32", 0), ((32, 32), 0.08, "f32", 3000),
-                                            ((11, 14), 0.25, "f32", 0)])
+                                            ((11, 14), 0.25, "f32", 0), ((24, 24), 0.27, "f32", 1500),
+                                            ((7, 9), 0.6, "f32", 0), ((64, 64), 0.1, "f32", 800)])
 def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample):
     _say(f"smooth_cov M={M} h={hb} {dt} sample={sample}")
     rng = np.random.default_rng(300 + sum(M))
@@ -231,8 +232,8 @@ def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample):
     tdt = torch.float64 if dt == "f64" else torch.float32
     gam = torch.empty(P, P, dtype=tdt, device="cuda:0")
     st = torch.empty(P, P, dtype=torch.int8, device="cuda:0")
-    F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F64 if dt == "f64" else F.FPCA_F32, dev(torch, C), dev(torch, G),
-                      dev(torch, mu), F.FPCA_K_EPANECHNIKOV, hb, gam, st)
+    F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F64 if dt == "f64" else F.FPCA_F32, dev(torch, C), 0.0,
+                      dev(torch, G), dev(torch, mu), F.FPCA_K_EPANECHNIKOV, hb, gam, st)
     h.sync()
     gam_h, st_h = host(gam), host(st)
     tol = 1e-10 if dt == "f64" else 1e-5
@@ -257,27 +258,35 @@ def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample):
     assert np.array_equal(gam_h, gam_h.T)
 
 
-def test_smooth_cov_analytic_common_grid(torch, F, h):
-    """C = NULL (complete common-grid design) equals passing C = 1 - delta."""
-    _say("smooth_cov analytic C")
+@pytest.mark.parametrize("M,hb", [((10, 10), 0.3), ((16, 16), 0.3), ((9, 12), 0.25)])
+def test_smooth_cov_analytic_common_grid(torch, F, h, M, hb):
+    """C = NULL (complete common-grid design, pair weight c_uniform off the
+    diagonal) equals passing C = c_uniform (1 - delta) explicitly."""
+    _say(f"smooth_cov analytic C M={M} h={hb}")
     rng = np.random.default_rng(11)
-    M = (10, 10)
-    P = 100
-    G = rng.standard_normal((P, P))
+    P = int(np.prod(M))
+    c0 = 0.37
+    G = rng.standard_normal((P, P)) * c0
     G = ((G + G.T) / 2).astype(np.float32)
     np.fill_diagonal(G, 0)
-    C = np.ones((P, P), np.float32)
+    C = np.full((P, P), c0, np.float32)
     np.fill_diagonal(C, 0)
+    mu = rng.standard_normal(P).astype(np.float32)
     outs = []
     for Cin in (None, dev(torch, C)):
         gam = torch.empty(P, P, dtype=torch.float32, device="cuda:0")
-        F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F32, Cin, dev(torch, G), None, F.FPCA_K_EPANECHNIKOV, 0.3, gam)
+        F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F32, Cin, c0, dev(torch, G), dev(torch, mu),
+                          F.FPCA_K_EPANECHNIKOV, hb, gam)
         outs.append(host(gam))
     h.sync()
-    rb, rst = oracle.smooth_cov_raw(M, 0.3, C.astype(np.float64), G.astype(np.float64))
-    ref = oracle.assemble_cov(rb.reshape(P, P), np.zeros(P))
+    rb, rst = oracle.smooth_cov_raw(M, hb, C.astype(np.float64), G.astype(np.float64))
+    ref = oracle.assemble_cov(rb.reshape(P, P), mu.astype(np.float64))
+    ok = (rst.reshape(P, P) == 0) & (rst.reshape(P, P).T == 0)
     for o in outs:
-        assert normwise_rel(o, ref) < 1e-5
+        assert normwise_rel(o, ref, ok) < 1e-5
+    with pytest.raises(F.FpcaError):
+        F.fpca_smooth_cov(h, F.Grid(M), F.FPCA_F32, None, 0.0, dev(torch, G), None, F.FPCA_K_EPANECHNIKOV, hb,
+                          torch.empty(P, P, dtype=torch.float32, device="cuda:0"))
 
 
 # ------------------------------------------------------------------ eigen
