@@ -59,16 +59,19 @@ __global__ void k_default_w(int64_t P, double wv, const uint8_t *mask, double *w
   if (p < P) w[p] = (mask && !mask[p]) ? 0.0 : wv;
 }
 
+
 // Partial products of Y^T = X^T Gamma over one K chunk (Gamma symmetric):
-// workgroup (column block of 64 nodes, K chunk), 4 waves x 16 columns, MFMA
-// 16x16x4 FP32 with the basis as the A operand and Gamma rows as B.
-template <int RB>
+// workgroup = (64 nodes, K chunk); 4 wavefronts x 16 nodes; MFMA 16x16x4 FP32
+// with the basis as the A operand and Gamma rows as the B operand. Tiles of 32
+// Gamma rows are prefetched into registers while the previous tile is used.
+template <int RB, bool VEC>
 __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__restrict__ G,
                                                     const float *__restrict__ X, int64_t kchunk,
                                                     float *__restrict__ part) {
   constexpr int RP = RB * 16;
-  __shared__ float As[16][64 + 4];
-  __shared__ float Xs[16][RP + 4];
+  constexpr int KT = 32;
+  __shared__ float As[2][KT][64 + 4];
+  __shared__ float Xs[2][KT][RP + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c0 = int64_t(blockIdx.x) * 64;
   const int64_t k0 = int64_t(blockIdx.y) * kchunk;
@@ -76,33 +79,62 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
   float4_t acc[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
-  const int ar = tid >> 4, ac = (tid & 15) * 4;
-  for (int64_t kb = k0; kb < k1; kb += 16) {
-    {
-      const int64_t q = kb + ar;
-      float v[4];
+  const int ar = tid >> 4, ac = (tid & 15) * 4;  // rows ar and ar+16, columns ac..ac+3
+  float ra[2][4], rx[2][4];
+  auto load = [&](int64_t kb) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = (q < k1 && c0 + ac + e < P) ? G[q * P + c0 + ac + e] : 0.f;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t q = kb + ar + 16 * h;
+      if (VEC && q < k1 && c0 + ac + 3 < P) {
+        const float4 v = *reinterpret_cast<const float4 *>(G + q * P + c0 + ac);
+        ra[h][0] = v.x; ra[h][1] = v.y; ra[h][2] = v.z; ra[h][3] = v.w;
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[ar][ac + e] = v[e];
+        for (int e = 0; e < 4; ++e) ra[h][e] = (q < k1 && c0 + ac + e < P) ? G[q * P + c0 + ac + e] : 0.f;
+      }
+      // basis rows kb..kb+31 are contiguous: KT*RP floats
+      const int o = (tid + 256 * h) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = (o + e) / RP, cc = (o + e) % RP;
+        const int64_t qq = kb + rr;
+        rx[h][e] = (o + e < KT * RP && qq < k1) ? X[qq * RP + cc] : 0.f;
+      }
     }
-    for (int e = tid; e < 16 * RP; e += 256) {
-      const int rr = e / RP, cc = e % RP;
-      const int64_t q = kb + rr;
-      Xs[rr][cc] = (q < k1) ? X[q * RP + cc] : 0.f;
-    }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[buf][ar + 16 * h][ac + e] = ra[h][e];
+      const int o = (tid + 256 * h) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (o + e < KT * RP) Xs[buf][(o + e) / RP][(o + e) % RP] = rx[h][e];
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) {
+    load(k0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += KT) {
+    const bool more = kb + KT < k1;
+    if (more) load(kb + KT);
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
       const int krow = kk + (lane >> 4);
-      const float b = As[krow][wave * 16 + (lane & 15)];
+      const float b = As[buf][krow][wave * 16 + (lane & 15)];
 #pragma unroll
       for (int mb = 0; mb < RB; ++mb) {
-        const float a = Xs[krow][mb * 16 + (lane & 15)];
+        const float a = Xs[buf][krow][mb * 16 + (lane & 15)];
         acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[mb], 0, 0, 0);
       }
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   // D[j][p]: row j = mb*16 + 4*(lane/16) + v, column p = c0 + wave*16 + lane%16.
   const int64_t p = c0 + wave * 16 + (lane & 15);
@@ -115,124 +147,187 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
   }
 }
 
-// Y[p, j] = sqrt(w_p) sum over K chunks of the partials (FP64).
-__global__ void k_panel_reduce(int64_t P, int rp, int nsplit, const float *__restrict__ part,
-                               const double *__restrict__ w, double *__restrict__ Y) {
-  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= P * rp) return;
-  const int64_t p = e / rp;
-  double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += double(part[int64_t(k) * P * rp + e]);
-  Y[e] = sqrt(w[p]) * s;
-}
-
-// FP64 product Y = W^1/2 Gamma X for FP64 storage (small grids).
+// FP64 product for FP64 storage (small grids): thread per (p, j); the Gamma
+// row stays in cache across the rp threads that share p.
 __global__ void k_panel_f64(int64_t P, int rp, const double *__restrict__ G, const double *__restrict__ X,
-                            const double *__restrict__ w, double *__restrict__ Y) {
+                            double *__restrict__ Yraw) {
   int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= P * rp) return;
   const int64_t p = e / rp;
   const int j = int(e % rp);
   double s = 0.0;
   for (int64_t q = 0; q < P; ++q) s += G[p * P + q] * X[q * rp + j];
-  Y[e] = sqrt(w[p]) * s;
+  Yraw[e] = s;
 }
 
-// Partial Gram products of two P x rp FP64 matrices over row chunks:
-// part[c][a][b] = sum_{p in chunk c} U[p][a] V[p][b].
-__global__ __launch_bounds__(256) void k_gram_part(int64_t P, int rp, int64_t chunk, const double *__restrict__ U,
-                                                    const double *__restrict__ V, double *__restrict__ part) {
-  const int64_t p0 = int64_t(blockIdx.x) * chunk, p1 = min(P, p0 + chunk);
-  for (int e = threadIdx.x; e < rp * rp; e += blockDim.x) {
+constexpr int GROWS = 64;  // rows per partial-Gram chunk
+
+// Finishes a product and starts the next orthonormalization, 64 rows per
+// workgroup: Y[p, j] = sqrt(w_p) * (sum of the K-split partials, or Yraw for
+// FP64 storage), then the chunk's partial Gram matrix:
+//   MODE 1: part = Y_c^T Y_c;  MODE 2: part = Q_c^T Y_c  (Rayleigh-Ritz).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce_gram(int64_t P, int rp, int nsplit, const float *__restrict__ part32,
+                                                      const double *__restrict__ Yraw, const double *__restrict__ w,
+                                                      const double *__restrict__ Q, double *__restrict__ Y,
+                                                      double *__restrict__ gpart) {
+  __shared__ double Ys[GROWS][65];
+  __shared__ double Qs[GROWS][65];
+  const int64_t p0 = int64_t(blockIdx.x) * GROWS;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < GROWS * rp; e += 256) {
+    const int rr = e / rp, j = e % rp;
+    const int64_t p = p0 + rr;
+    double v = 0.0, qv = 0.0;
+    if (p < P) {
+      const int64_t o = p * rp + j;
+      if (part32) {
+        for (int k = 0; k < nsplit; ++k) v += double(part32[int64_t(k) * P * rp + o]);
+      } else {
+        v = Yraw[o];
+      }
+      v *= sqrt(w[p]);
+      Y[o] = v;
+      if (MODE == 2) qv = Q[o];
+    }
+    Ys[rr][j] = v;
+    if (MODE == 2) Qs[rr][j] = qv;
+  }
+  __syncthreads();
+  for (int e = tid; e < rp * rp; e += 256) {
     const int a = e / rp, b = e % rp;
     double s = 0.0;
-    for (int64_t p = p0; p < p1; ++p) s += U[p * rp + a] * V[p * rp + b];
-    part[int64_t(blockIdx.x) * rp * rp + e] = s;
+    for (int rr = 0; rr < GROWS; ++rr) s += (MODE == 2 ? Qs[rr][a] : Ys[rr][a]) * Ys[rr][b];
+    gpart[int64_t(blockIdx.x) * rp * rp + e] = s;
   }
 }
 
-// One workgroup: G = sum of partials; Cholesky G = R^T R with numerically
-// dependent columns dropped (pivot <= 1e-12 of the column's squared norm);
-// Rinv = R^{-1} with the dropped columns zeroed; act[j] = 1 for kept columns.
-__global__ __launch_bounds__(256) void k_chol(int rp, int nparts, const double *__restrict__ part,
-                                               double *__restrict__ Rinv, int *__restrict__ act) {
-  __shared__ double Gs[64][65];
-  __shared__ double L[64][65];
-  __shared__ double Ri[64][65];
-  __shared__ int keep[64];
+// One workgroup: G = sum of the partial Gram matrices; then one wavefront
+// factors G = L L^T right-looking with the rows in registers (column j is
+// broadcast through LDS), dropping numerically dependent columns (pivot <=
+// 1e-12 of the column's squared norm), and inverts L by forward substitution
+// (lane j owns column j of L^{-1}). Rinv = R^{-1} = (L^{-1})^T with the dropped
+// columns zeroed; act[j] = 1 for kept columns.
+template <int RP>
+__global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restrict__ part, double *__restrict__ Rinv,
+                                               int *__restrict__ act) {
+  __shared__ double Gs[RP][RP + 1];
+  __shared__ double Ls[RP][RP + 1];
+  __shared__ double col[RP];
+  __shared__ int keep[RP];
   const int tid = threadIdx.x;
-  for (int e = tid; e < rp * rp; e += blockDim.x) {
+  for (int e = tid; e < RP * RP; e += 256) {
     double s = 0.0;
-    for (int c = 0; c < nparts; ++c) s += part[int64_t(c) * rp * rp + e];
-    Gs[e / rp][e % rp] = s;
-    L[e / rp][e % rp] = 0.0;
+    for (int c = 0; c < nparts; ++c) s += part[int64_t(c) * RP * RP + e];
+    Gs[e / RP][e % RP] = s;
   }
   __syncthreads();
-  for (int j = 0; j < rp; ++j) {
-    if (tid == 0) {
-      double dj = Gs[j][j];
-      for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
-      const bool ok = Gs[j][j] > 0.0 && dj > 1e-12 * Gs[j][j];
-      keep[j] = ok ? 1 : 0;
-      L[j][j] = ok ? sqrt(dj) : 1.0;
-    }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < rp; i += blockDim.x) {
-      double v = 0.0;
-      if (keep[j]) {
-        v = Gs[i][j];
-        for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-        v /= L[j][j];
+  {
+    // thread i < RP owns row i; the others take part in the barriers only
+    const int i = tid;
+    double a[RP];
+#pragma unroll
+    for (int k = 0; k < RP; ++k) a[k] = i < RP ? Gs[i][k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+      const double djj = Gs[j][j];  // original diagonal
+      if (i == j) col[j] = a[j];
+      __syncthreads();
+      const double piv = col[j];
+      const bool ok = djj > 0.0 && piv > 1e-12 * djj;
+      const double ljj = ok ? sqrt(piv) : 1.0;
+      const double lij = (i > j && i < RP && ok) ? a[j] / ljj : 0.0;
+      __syncthreads();
+      if (i < RP) {
+        if (i == j) {
+          Ls[j][j] = ljj;
+          keep[j] = ok ? 1 : 0;
+        }
+        if (i > j) Ls[i][j] = lij;
+        col[i] = (i > j) ? lij : 0.0;
       }
-      L[i][j] = v;
+      __syncthreads();
+#pragma unroll
+      for (int k = j + 1; k < RP; ++k) a[k] -= lij * col[k];
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // R = L^T (upper). Column j of R^{-1}: solve R x = e_j by back substitution.
-  for (int j = tid; j < rp; j += blockDim.x) {
-    for (int i = rp - 1; i >= 0; --i) {
+  if (tid < RP) {
+    // column j = tid of X = L^{-1}: X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i]
+    const int j = tid;
+    double x[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
       double v = (i == j) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) v -= L[k][i] * Ri[k][j];
-      Ri[i][j] = (i <= j) ? v / L[i][i] : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= Ls[i][k] * x[k];
+      x[i] = (i >= j) ? v / Ls[i][i] : 0.0;
     }
+    // Rinv[j][i] = X[i][j]; column i of Rinv zeroed if dropped
+#pragma unroll
+    for (int i = 0; i < RP; ++i) Rinv[j * RP + i] = keep[i] ? x[i] : 0.0;
+    act[j] = keep[j];
+  }
+}
+
+// Q = Y Rinv (FP64, 64 rows per workgroup); optionally the next basis
+// X = W^1/2 Q in storage type T, and the chunk's partial Gram of Q.
+template <typename T, bool GRAM>
+__global__ __launch_bounds__(256) void k_apply_rinv(int64_t P, int rp, const double *__restrict__ Y,
+                                                     const double *__restrict__ Rinv, const double *__restrict__ w,
+                                                     double *__restrict__ Q, T *__restrict__ X,
+                                                     double *__restrict__ gpart) {
+  __shared__ double Ys[GROWS][65];
+  __shared__ double Ri[64][65];
+  const int64_t p0 = int64_t(blockIdx.x) * GROWS;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < rp * rp; e += 256) Ri[e / rp][e % rp] = Rinv[e];
+  for (int e = tid; e < GROWS * rp; e += 256) {
+    const int64_t p = p0 + e / rp;
+    Ys[e / rp][e % rp] = p < P ? Y[p * rp + e % rp] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < rp * rp; e += blockDim.x) {
-    const int i = e / rp, j = e % rp;
-    Rinv[e] = keep[j] ? Ri[i][j] : 0.0;
+  double qv[GROWS * 64 / 256];
+  int cnt = 0;
+  for (int e = tid; e < GROWS * rp; e += 256, ++cnt) {
+    const int rr = e / rp, j = e % rp;
+    double s = 0.0;
+    for (int i = 0; i <= j; ++i) s += Ys[rr][i] * Ri[i][j];
+    qv[cnt] = s;
+    const int64_t p = p0 + rr;
+    if (p < P) {
+      Q[p * rp + j] = s;
+      if (X) X[p * rp + j] = T(sqrt(w[p]) * s);
+    }
   }
-  for (int j = tid; j < rp; j += blockDim.x) act[j] = keep[j];
+  if (!GRAM) return;
+  __syncthreads();
+  cnt = 0;
+  for (int e = tid; e < GROWS * rp; e += 256, ++cnt) Ys[e / rp][e % rp] = qv[cnt];
+  __syncthreads();
+  for (int e = tid; e < rp * rp; e += 256) {
+    const int a = e / rp, b = e % rp;
+    double s = 0.0;
+    for (int rr = 0; rr < GROWS; ++rr) s += Ys[rr][a] * Ys[rr][b];
+    gpart[int64_t(blockIdx.x) * rp * rp + e] = s;
+  }
 }
 
-// Q = Y Rinv (FP64) and the next basis X = W^1/2 Q in storage type T.
-template <typename T>
-__global__ void k_apply_rinv(int64_t P, int rp, const double *__restrict__ Y, const double *__restrict__ Rinv,
-                             const double *__restrict__ w, double *__restrict__ Q, T *__restrict__ X) {
-  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= P * rp) return;
-  const int64_t p = e / rp;
-  const int j = int(e % rp);
-  double s = 0.0;
-  for (int i = 0; i <= j; ++i) s += Y[p * rp + i] * Rinv[i * rp + j];
-  Q[e] = s;
-  if (X) X[e] = T(sqrt(w[p]) * s);
-}
-
-// One workgroup: B = sum of partials restricted to the active columns,
-// symmetrized; cyclic Jacobi with round-robin ordering (disjoint rotations
-// applied together); eigenvalues sorted descending (stable); outputs the top k
-// values, their eigenvectors mapped back to the rp basis columns, and FVE.
+// One workgroup: B = sum of the partials restricted to the active columns,
+// symmetrized; cyclic Jacobi with round-robin ordering: the ne/2 disjoint
+// rotations of a step are applied together, B' = J^T B J and V' = V J, each
+// element computed from the previous buffer. Eigenvalues sorted descending
+// (stable); outputs the top k, their eigenvectors in the rp basis, and FVE.
 __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const double *__restrict__ part,
                                                   const int *__restrict__ act, int k, double *__restrict__ evals,
                                                   double *__restrict__ fve, double *__restrict__ Uk) {
-  __shared__ double B[64][65];
-  __shared__ double V[64][65];
+  __shared__ double Bb[2][64][65];
+  __shared__ double Vb[2][64][65];
   __shared__ double cs[32], sn[32];
-  __shared__ int pa[32], pb[32];
+  __shared__ int partner[64], role[64], pidx[64];
   __shared__ int idx[64];
-  __shared__ int n_s, ne_s;
-  __shared__ double red[1024];
-  __shared__ int stop;
+  __shared__ int n_s, ne_s, stop;
+  __shared__ double red_off[16], red_tot[16];
   const int tid = threadIdx.x;
   if (tid == 0) {
     int n = 0;
@@ -255,94 +350,89 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
       }
       v = 0.5 * (s1 + s2);
     }
-    B[a][b] = v;
-    V[a][b] = (a == b) ? 1.0 : 0.0;
+    Bb[0][a][b] = v;
+    Vb[0][a][b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int npair = ne / 2;
+  int cur = 0;
   for (int sweep = 0; sweep < 60 && ne >= 2; ++sweep) {
-    // convergence: off-diagonal mass against the whole
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < ne * ne; e += blockDim.x) {
       const int a = e / ne, b = e % ne;
-      const double v = B[a][b] * B[a][b];
+      const double v = Bb[cur][a][b] * Bb[cur][a][b];
       tot += v;
       if (a != b) off += v;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+    if ((tid & 63) == 0) {
+      red_off[tid >> 6] = off;
+      red_tot[tid >> 6] = tot;
     }
-    if (tid == 0) stop = !(offs > 1e-30 * red[0]);
+    __syncthreads();
+    if (tid == 0) {
+      double so = 0.0, st = 0.0;
+      for (int wv = 0; wv < int(blockDim.x / 64); ++wv) {
+        so += red_off[wv];
+        st += red_tot[wv];
+      }
+      stop = !(so > 1e-28 * st);
+    }
     __syncthreads();
     if (stop) break;
-    for (int st = 0; st < ne - 1; ++st) {
+    for (int step = 0; step < ne - 1; ++step) {
       if (tid < npair) {
         int a, b;
         if (tid == 0) {
           a = ne - 1;
-          b = st;
+          b = step;
         } else {
-          a = (st + tid) % (ne - 1);
-          b = (st - tid + ne - 1) % (ne - 1);
+          a = (step + tid) % (ne - 1);
+          b = (step - tid + ne - 1) % (ne - 1);
         }
-        const double apq = B[a][b];
+        const double apq = Bb[cur][a][b];
         double c = 1.0, s = 0.0;
         if (apq != 0.0) {
-          const double tau = (B[b][b] - B[a][a]) / (2.0 * apq);
+          const double tau = (Bb[cur][b][b] - Bb[cur][a][a]) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
         }
-        pa[tid] = a;
-        pb[tid] = b;
+        partner[a] = b;
+        partner[b] = a;
+        role[a] = 0;
+        role[b] = 1;
+        pidx[a] = tid;
+        pidx[b] = tid;
         cs[tid] = c;
         sn[tid] = s;
       }
       __syncthreads();
-      // rows: B <- J^T B
-      for (int e = tid; e < npair * ne; e += blockDim.x) {
-        const int m = e / ne, col = e % ne;
-        const int a = pa[m], b = pb[m];
-        const double c = cs[m], s = sn[m];
-        const double x = B[a][col], y = B[b][col];
-        B[a][col] = c * x - s * y;
-        B[b][col] = s * x + c * y;
+      const int nxt = cur ^ 1;
+      for (int e = tid; e < ne * ne; e += blockDim.x) {
+        const int i = e / ne, j = e % ne;
+        const int pi = partner[i], pj = partner[j];
+        const double ci = cs[pidx[i]], si = role[i] == 0 ? -sn[pidx[i]] : sn[pidx[i]];
+        const double cj = cs[pidx[j]], sj = role[j] == 0 ? -sn[pidx[j]] : sn[pidx[j]];
+        const double bj = Bb[cur][i][j] * cj + Bb[cur][i][pj] * sj;
+        const double bpj = Bb[cur][pi][j] * cj + Bb[cur][pi][pj] * sj;
+        Bb[nxt][i][j] = ci * bj + si * bpj;
+        Vb[nxt][i][j] = Vb[cur][i][j] * cj + Vb[cur][i][pj] * sj;
       }
       __syncthreads();
-      // columns: B <- B J, V <- V J
-      for (int e = tid; e < npair * ne; e += blockDim.x) {
-        const int m = e / ne, row = e % ne;
-        const int a = pa[m], b = pb[m];
-        const double c = cs[m], s = sn[m];
-        const double x = B[row][a], y = B[row][b];
-        B[row][a] = c * x - s * y;
-        B[row][b] = s * x + c * y;
-        const double vx = V[row][a], vy = V[row][b];
-        V[row][a] = c * vx - s * vy;
-        V[row][b] = s * vx + c * vy;
-      }
-      __syncthreads();
+      cur = nxt;
     }
   }
-  // Sort the n real eigenvalues (the padding index, if any, is excluded).
   __shared__ int order[64];
   __shared__ double possum;
   if (tid < n) {
-    const double v = B[tid][tid];
+    const double v = Bb[cur][tid][tid];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double u = B[j][j];
+      const double u = Bb[cur][j][j];
       if (u > v || (u == v && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -350,14 +440,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
   if (tid == 0) {
     double s = 0.0;
     for (int j = 0; j < n; ++j)
-      if (B[j][j] > 0.0) s += B[j][j];
+      if (Bb[cur][j][j] > 0.0) s += Bb[cur][j][j];
     possum = s;
   }
   __syncthreads();
   if (tid == 0) {
     double cum = 0.0;
     for (int l = 0; l < k; ++l) {
-      const double v = l < n ? B[order[l]][order[l]] : 0.0;
+      const double v = l < n ? Bb[cur][order[l]][order[l]] : 0.0;
       cum += v;
       evals[l] = v;
       fve[l] = possum > 0.0 ? cum / possum : 0.0;
@@ -367,85 +457,117 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
   __syncthreads();
   for (int e = tid; e < n * k; e += blockDim.x) {
     const int a = e / k, l = e % k;
-    if (l < n) Uk[int64_t(idx[a]) * k + l] = V[a][order[l]];
+    if (l < n) Uk[int64_t(idx[a]) * k + l] = Vb[cur][a][order[l]];
   }
 }
 
-// One workgroup per eigenvector l: psi = Q U[:, l], phi = psi / sqrt(w) (0 where
-// w = 0), sign rule, written column-major into efuns.
-template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(int64_t P, int rp, int k, const double *__restrict__ Q,
-                                                   const double *__restrict__ Uk, const double *__restrict__ w,
-                                                   double *__restrict__ phi, T *__restrict__ efuns) {
-  __shared__ double r1[256], r2[256], r3[256];
-  __shared__ long long ri[256];
-  const int l = blockIdx.x, tid = threadIdx.x;
-  double s1 = 0.0, s2 = 0.0, mx = 0.0;
-  for (int64_t p = tid; p < P; p += blockDim.x) {
+// phi[l][p] = (Q U)[p][l] / sqrt(w_p) (0 where w_p = 0), with per-workgroup
+// partial sums of w phi, w |phi| and max |phi| for the sign rule.
+__global__ __launch_bounds__(256) void k_phi(int64_t P, int rp, int k, const double *__restrict__ Q,
+                                              const double *__restrict__ Uk, const double *__restrict__ w,
+                                              double *__restrict__ phi, double *__restrict__ red) {
+  __shared__ double r1[4], r2[4], r3[4];
+  const int l = blockIdx.y, tid = threadIdx.x;
+  const int64_t p = int64_t(blockIdx.x) * 256 + tid;
+  double f = 0.0, wp = 0.0;
+  if (p < P) {
     double v = 0.0;
     for (int i = 0; i < rp; ++i) v += Q[p * rp + i] * Uk[int64_t(i) * k + l];
-    const double f = w[p] > 0.0 ? v / sqrt(w[p]) : 0.0;
+    wp = w[p];
+    f = wp > 0.0 ? v / sqrt(wp) : 0.0;
     phi[int64_t(l) * P + p] = f;
-    s1 += w[p] * f;
-    s2 += w[p] * fabs(f);
-    mx = fmax(mx, fabs(f));
   }
-  r1[tid] = s1;
-  r2[tid] = s2;
-  r3[tid] = mx;
+  double s1 = wp * f, s2 = wp * fabs(f), mx = fabs(f);
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+    mx = fmax(mx, __shfl_xor(mx, o));
+  }
+  if ((tid & 63) == 0) {
+    r1[tid >> 6] = s1;
+    r2[tid >> 6] = s2;
+    r3[tid >> 6] = mx;
+  }
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      r1[tid] += r1[tid + s];
-      r2[tid] += r2[tid + s];
-      r3[tid] = fmax(r3[tid], r3[tid + s]);
+  if (tid == 0) {
+    const int64_t o = (int64_t(l) * gridDim.x + blockIdx.x) * 3;
+    red[o] = r1[0] + r1[1] + r1[2] + r1[3];
+    red[o + 1] = r2[0] + r2[1] + r2[2] + r2[3];
+    red[o + 2] = fmax(fmax(r3[0], r3[1]), fmax(r3[2], r3[3]));
+  }
+}
+
+// One workgroup per eigenvector: sign rule from the partial sums (the
+// lowest-index tie-break scans phi only when sum w phi is negligible), then the
+// signed eigenfunction is written in storage type T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_write(int64_t P, int nblk, const double *__restrict__ phi,
+                                                     const double *__restrict__ red, T *__restrict__ efuns) {
+  __shared__ double S1, S2, MX;
+  __shared__ long long first[256];
+  const int l = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+      const int64_t o = (int64_t(l) * nblk + i) * 3;
+      a += red[o];
+      b += red[o + 1];
+      m = fmax(m, red[o + 2]);
     }
-    __syncthreads();
+    S1 = a;
+    S2 = b;
+    MX = m;
   }
-  const double S1 = r1[0], S2 = r2[0], MX = r3[0];
   __syncthreads();
+  const double *f = phi + int64_t(l) * P;
   bool neg;
   if (fabs(S1) >= 1e-8 * S2) {
     neg = S1 < 0.0;
   } else {
-    long long first = P;
-    for (int64_t p = tid; p < P; p += blockDim.x)
-      if (fabs(phi[int64_t(l) * P + p]) >= (1.0 - 1e-6) * MX) {
-        first = p;
+    long long fi = P;
+    for (int64_t p = tid; p < P; p += 256)
+      if (fabs(f[p]) >= (1.0 - 1e-6) * MX) {
+        fi = p;
         break;
       }
-    ri[tid] = first;
+    first[tid] = fi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) ri[tid] = min(ri[tid], ri[tid + s]);
+      if (tid < s) first[tid] = min(first[tid], first[tid + s]);
       __syncthreads();
     }
-    neg = (ri[0] < P) && phi[int64_t(l) * P + ri[0]] < 0.0;
+    neg = first[0] < P && f[first[0]] < 0.0;
   }
   const double sg = neg ? -1.0 : 1.0;
-  for (int64_t p = tid; p < P; p += blockDim.x) efuns[int64_t(l) * P + p] = T(sg * phi[int64_t(l) * P + p]);
+  for (int64_t p = tid; p < P; p += 256) efuns[int64_t(l) * P + p] = T(sg * f[p]);
 }
 
 inline unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
+
+template <int RP>
+void launch_chol(fpca_context *ctx, int nparts, const double *part, double *Rinv, int *act) {
+  hipLaunchKernelGGL(k_chol<RP>, dim3(1), dim3(256), 0, ctx->stream, nparts, part, Rinv, act);
+}
 
 template <typename T>
 int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k,
              int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
   const int r = k + oversample;
   const int rp = ((r + 15) / 16) * 16;
+  const bool f32 = sizeof(T) == 4;
   // K split of the panel product: enough workgroups to fill the chip
   const int64_t colblocks = (P + 63) / 64;
   int64_t nsplit = (4 * int64_t(ctx->num_cus) + colblocks - 1) / colblocks;
   if (nsplit < 1) nsplit = 1;
-  int64_t kchunk = ((P + nsplit - 1) / nsplit + 15) / 16 * 16;
+  int64_t kchunk = ((P + nsplit - 1) / nsplit + 31) / 32 * 32;
   nsplit = (P + kchunk - 1) / kchunk;
-  const int64_t gchunk = 256;
-  const int64_t ngram = (P + gchunk - 1) / gchunk;
-  const bool f32 = sizeof(T) == 4;
+  const int64_t ngram = (P + GROWS - 1) / GROWS;
+  const int64_t nphi = (P + 255) / 256;
   size_t need = carve_bytes(P, 8) + carve_bytes(P * rp, sizeof(T)) + 3 * carve_bytes(P * rp, 8) +
                 carve_bytes(ngram * rp * rp, 8) + carve_bytes(rp * rp, 8) + carve_bytes(rp, 4) +
-                carve_bytes(rp * k, 8) + 2 * carve_bytes(k, 8) + carve_bytes(P * k, 8);
-  if (f32) need += carve_bytes(nsplit * P * rp, 4);
+                carve_bytes(rp * k, 8) + 2 * carve_bytes(k, 8) + carve_bytes(P * k, 8) +
+                carve_bytes(nphi * k * 3, 8);
+  need += f32 ? carve_bytes(nsplit * P * rp, 4) : carve_bytes(P * rp, 8);
   if (int rc = ws_reserve(ctx, need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
   double *w = cv.take<double>(P);
@@ -460,7 +582,9 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
   double *ev_d = cv.take<double>(k);
   double *fve_d = cv.take<double>(k);
   double *phi = cv.take<double>(P * k);
+  double *red = cv.take<double>(nphi * k * 3);
   float *part = f32 ? cv.take<float>(nsplit * P * rp) : nullptr;
+  double *Yraw = f32 ? nullptr : cv.take<double>(P * rp);
 
   if (quad_w) {
     FPCA_HIP(hipMemcpyAsync(w, quad_w, sizeof(double) * P, hipMemcpyDeviceToDevice, ctx->stream));
@@ -473,55 +597,76 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
   hipLaunchKernelGGL(k_test_matrix<T>, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, seed, P, r, rp, w, X);
   FPCA_LAUNCH_CHECK("test_matrix");
 
-  auto product = [&](double *out) -> int {
+  // Y (or Z) = W^1/2 Gamma X, then the partial Gram (MODE 1: of itself, MODE 2: Q^T Y)
+  auto product = [&](double *out, int mode) -> int {
     if constexpr (sizeof(T) == 4) {
       dim3 grd((unsigned)colblocks, (unsigned)nsplit);
+      const bool vec = (P % 4 == 0) && ((reinterpret_cast<uintptr_t>(gamma) & 15) == 0);
+#define PANEL(RB)                                                                                          \
+  if (vec)                                                                                                 \
+    hipLaunchKernelGGL((k_panel_f32<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,   \
+                       (const float *)X, kchunk, part);                                                    \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_panel_f32<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,  \
+                       (const float *)X, kchunk, part);
       switch (rp / 16) {
-        case 1: hipLaunchKernelGGL(k_panel_f32<1>, grd, dim3(256), 0, ctx->stream, P, (const float *)gamma, (const float *)X, kchunk, part); break;
-        case 2: hipLaunchKernelGGL(k_panel_f32<2>, grd, dim3(256), 0, ctx->stream, P, (const float *)gamma, (const float *)X, kchunk, part); break;
-        case 3: hipLaunchKernelGGL(k_panel_f32<3>, grd, dim3(256), 0, ctx->stream, P, (const float *)gamma, (const float *)X, kchunk, part); break;
-        default: hipLaunchKernelGGL(k_panel_f32<4>, grd, dim3(256), 0, ctx->stream, P, (const float *)gamma, (const float *)X, kchunk, part); break;
+        case 1: PANEL(1) break;
+        case 2: PANEL(2) break;
+        case 3: PANEL(3) break;
+        default: PANEL(4) break;
       }
+#undef PANEL
       FPCA_LAUNCH_CHECK("panel_f32");
-      hipLaunchKernelGGL(k_panel_reduce, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, P, rp, int(nsplit), part, w, out);
-      FPCA_LAUNCH_CHECK("panel_reduce");
     } else {
       hipLaunchKernelGGL(k_panel_f64, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, P, rp, (const double *)gamma,
-                         (const double *)X, w, out);
+                         (const double *)X, Yraw);
       FPCA_LAUNCH_CHECK("panel_f64");
     }
+    if (mode == 2)
+      hipLaunchKernelGGL(k_reduce_gram<2>, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, int(nsplit), part,
+                         Yraw, w, Q, out, gpart);
+    else
+      hipLaunchKernelGGL(k_reduce_gram<1>, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, int(nsplit), part,
+                         Yraw, w, Q, out, gpart);
+    FPCA_LAUNCH_CHECK("reduce_gram");
     return FPCA_OK;
   };
-  auto cholqr = [&](const double *Yin) -> int {
-    // two CholeskyQR passes: Y -> Q1 (in Z) -> Q
-    const double *src = Yin;
-    double *dst[2] = {Z, Q};
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_gram_part, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, gchunk, src, src, gpart);
-      FPCA_LAUNCH_CHECK("gram_part");
-      hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, ctx->stream, rp, int(ngram), gpart, Rinv, act);
-      FPCA_LAUNCH_CHECK("chol");
-      hipLaunchKernelGGL(k_apply_rinv<T>, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, P, rp, src, Rinv, w, dst[pass],
-                         pass == 1 ? X : (T *)nullptr);
-      FPCA_LAUNCH_CHECK("apply_rinv");
-      src = dst[pass];
+  auto chol = [&]() -> int {
+    switch (rp) {
+      case 16: launch_chol<16>(ctx, int(ngram), gpart, Rinv, act); break;
+      case 32: launch_chol<32>(ctx, int(ngram), gpart, Rinv, act); break;
+      case 48: launch_chol<48>(ctx, int(ngram), gpart, Rinv, act); break;
+      default: launch_chol<64>(ctx, int(ngram), gpart, Rinv, act); break;
     }
+    FPCA_LAUNCH_CHECK("chol");
+    return FPCA_OK;
+  };
+  // CholeskyQR2 of Y (whose partial Gram is already in gpart): Y -> Z -> Q, X.
+  auto cholqr2 = [&]() -> int {
+    if (int rc = chol()) return rc;
+    hipLaunchKernelGGL((k_apply_rinv<T, true>), dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, Y, Rinv, w, Z,
+                       (T *)nullptr, gpart);
+    FPCA_LAUNCH_CHECK("apply_rinv");
+    if (int rc = chol()) return rc;
+    hipLaunchKernelGGL((k_apply_rinv<T, false>), dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, Z, Rinv, w,
+                       Q, X, (double *)nullptr);
+    FPCA_LAUNCH_CHECK("apply_rinv");
     return FPCA_OK;
   };
 
-  if (int rc = product(Y)) return rc;
-  if (int rc = cholqr(Y)) return rc;
+  if (int rc = product(Y, 1)) return rc;
+  if (int rc = cholqr2()) return rc;
   for (int it = 0; it < 2 * power_iters; ++it) {
-    if (int rc = product(Y)) return rc;
-    if (int rc = cholqr(Y)) return rc;
+    if (int rc = product(Y, 1)) return rc;
+    if (int rc = cholqr2()) return rc;
   }
-  if (int rc = product(Z)) return rc;  // Z = A Q
-  hipLaunchKernelGGL(k_gram_part, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, gchunk, Q, Z, gpart);
-  FPCA_LAUNCH_CHECK("rr_gram");
+  if (int rc = product(Z, 2)) return rc;  // Z = A Q and the partials of Q^T Z
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, ctx->stream, rp, int(ngram), gpart, act, k, ev_d, fve_d, Uk);
   FPCA_LAUNCH_CHECK("jacobi");
-  hipLaunchKernelGGL(k_finalize<T>, dim3(unsigned(k)), dim3(256), 0, ctx->stream, P, rp, k, Q, Uk, w, phi, efuns);
-  FPCA_LAUNCH_CHECK("finalize");
+  hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, rp, k, Q, Uk, w, phi, red);
+  FPCA_LAUNCH_CHECK("phi");
+  hipLaunchKernelGGL(k_sign_write<T>, dim3(unsigned(k)), dim3(256), 0, ctx->stream, P, int(nphi), phi, red, efuns);
+  FPCA_LAUNCH_CHECK("sign_write");
   std::vector<double> hb(2 * k);
   FPCA_HIP(hipMemcpyAsync(hb.data(), ev_d, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
   FPCA_HIP(hipMemcpyAsync(hb.data() + k, fve_d, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
