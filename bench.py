@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--gram-prec", choices=["bf16x3", "f32"], default="bf16x3",
+                    help="precision of the binning Gram product (bf16 hi/lo x3 with FP32 accumulation, or FP32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -90,6 +92,7 @@ def main():
     dd = PL.to_device(ds)
     bufs = PL.alloc(dd, ds.k, with_status=True, analytic_C=True)
     stream = torch.cuda.current_stream()
+    gram_prec = F.FPCA_PREC_BF16X3 if args.gram_prec == "bf16x3" else F.FPCA_PREC_F32
 
     def step(record=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if record is not None else None
@@ -99,7 +102,7 @@ def main():
         F.fpca_smooth_mean(h, dd.grid_mean, dd.dtype, bufs.c, bufs.s, F.FPCA_K_EPANECHNIKOV, ds.h_mean,
                            bufs.mu, bufs.mu_status)
         if ev: ev[1].record(stream)
-        F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_COV, dd.design, dd.dtype, F.FPCA_PREC_F32, dd.n, None, None,
+        F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_COV, dd.design, dd.dtype, gram_prec, dd.n, None, None,
                    dd.y, None, 0, bufs.extra.setdefault("Cs", torch.empty_like(bufs.G)), bufs.G)
         if ev: ev[2].record(stream)
         F.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, None, PL.uniform_pair_weight(dd), bufs.G, bufs.mu,
@@ -152,7 +155,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "d=2 common grid 64x64, n=%d Matern-1.5 GP fields, cov 64^4 nodes, h=0.1, "
                                "randomized eig k=20 p=10 q=2" % args.n,
-                   "n": args.n, "grid": [64, 64], "cov_nodes": nodes, "h": ds.h_cov},
+                   "n": args.n, "grid": [64, 64], "cov_nodes": nodes, "h": ds.h_cov,
+                   "gram_prec": args.gram_prec},
         "stages_ms": stage_ms,
         "smooth_cov_pts_per_s": nodes / (sc_ms / 1e3),
         "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (all its launches)", "achieved": achieved,

@@ -17,6 +17,10 @@ struct fpca_context {
   void *ws = nullptr;
   size_t ws_size = 0;
   size_t ws_limit = 0;  // 0 = unlimited
+  // Second arena for the split bf16 operands of the Gram product (its inputs
+  // may live in the first arena).
+  void *ws2 = nullptr;
+  size_t ws2_size = 0;
   // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
   int *d_flags = nullptr;
   int *h_flags = nullptr;  // pinned mirror
@@ -40,8 +44,9 @@ int hip_fail(hipError_t e, const char *what);
     if (e_ != hipSuccess) return fpca::hip_fail(e_, what);  \
   } while (0)
 
-// Scratch arena: ensure at least `bytes`; returns FPCA_OK or an error.
+// Scratch arenas: ensure at least `bytes`; returns FPCA_OK or an error.
 int ws_reserve(fpca_context *ctx, size_t bytes);
+int ws2_reserve(fpca_context *ctx, size_t bytes);
 
 // Bump allocator over the reserved arena (256-byte aligned carving).
 struct Carver {

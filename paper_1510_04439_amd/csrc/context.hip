@@ -87,6 +87,26 @@ int ws_reserve(fpca_context *ctx, size_t bytes) {
   return FPCA_OK;
 }
 
+int ws2_reserve(fpca_context *ctx, size_t bytes) {
+  if (bytes <= ctx->ws2_size) return FPCA_OK;
+  if (ctx->ws_limit && bytes + ctx->ws_size > ctx->ws_limit)
+    return set_error(FPCA_ERR_WORKSPACE, "scratch request %zu bytes exceeds the limit %zu", bytes, ctx->ws_limit);
+  if (ctx->ws2) {
+    FPCA_HIP(hipStreamSynchronize(ctx->stream));
+    FPCA_HIP(hipFree(ctx->ws2));
+    ctx->ws2 = nullptr;
+    ctx->ws2_size = 0;
+  }
+  hipError_t e = hipMalloc(&ctx->ws2, bytes);
+  if (e != hipSuccess) {
+    ctx->ws2 = nullptr;
+    (void)hipGetLastError();
+    return set_error(FPCA_ERR_WORKSPACE, "hipMalloc of %zu scratch bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  ctx->ws2_size = bytes;
+  return FPCA_OK;
+}
+
 template <typename T>
 __global__ void k_fill(T *__restrict__ p, T v, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -152,6 +172,7 @@ int fpca_destroy(fpca_handle ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->ws2) (void)hipFree(ctx->ws2);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   delete ctx;

@@ -60,6 +60,20 @@ __global__ void k_default_w(int64_t P, double wv, const uint8_t *mask, double *w
 }
 
 
+// sum_{c < n} a[c * stride] with eight independent accumulators, so that the
+// loads are in flight together (fixed summation order: deterministic).
+template <typename T>
+__device__ inline double strided_sum(const T *__restrict__ a, int n, int64_t stride) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += double(a[int64_t(c + u) * stride]);
+  }
+  for (; c < n; ++c) s[0] += double(a[int64_t(c) * stride]);
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Partial products of Y^T = X^T Gamma over one K chunk (Gamma symmetric):
 // workgroup = (64 nodes, K chunk); 4 wavefronts x 16 nodes; MFMA 16x16x4 FP32
 // with the basis as the A operand and Gamma rows as the B operand. Tiles of 32
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(256) void k_reduce_gram(int64_t P, int rp, int nspl
     if (p < P) {
       const int64_t o = p * rp + j;
       if (part32) {
-        for (int k = 0; k < nsplit; ++k) v += double(part32[int64_t(k) * P * rp + o]);
+        v = strided_sum(part32 + o, nsplit, P * rp);
       } else {
         v = Yraw[o];
       }
@@ -217,9 +231,7 @@ __global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restri
   __shared__ int keep[RP];
   const int tid = threadIdx.x;
   for (int e = tid; e < RP * RP; e += 256) {
-    double s = 0.0;
-    for (int c = 0; c < nparts; ++c) s += part[int64_t(c) * RP * RP + e];
-    Gs[e / RP][e % RP] = s;
+    Gs[e / RP][e % RP] = strided_sum(part + e, nparts, int64_t(RP) * RP);
   }
   __syncthreads();
   {
@@ -343,11 +355,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
     double v = 0.0;
     if (a < n && b < n) {
       const int64_t o1 = int64_t(idx[a]) * rp + idx[b], o2 = int64_t(idx[b]) * rp + idx[a];
-      double s1 = 0.0, s2 = 0.0;
-      for (int c = 0; c < nparts; ++c) {
-        s1 += part[int64_t(c) * rp * rp + o1];
-        s2 += part[int64_t(c) * rp * rp + o2];
-      }
+      const double s1 = strided_sum(part + o1, nparts, int64_t(rp) * rp);
+      const double s2 = strided_sum(part + o2, nparts, int64_t(rp) * rp);
       v = 0.5 * (s1 + s2);
     }
     Bb[0][a][b] = v;

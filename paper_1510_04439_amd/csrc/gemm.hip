@@ -162,6 +162,136 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
       }
 }
 
+// Precision split for the BF16x3 product: A (K x N row-major FP32) ->
+// Th = bf16(A^T), Tl = bf16(A^T - Th), both N x Kp with K contiguous and the
+// rows padded with zeros to Kp (a multiple of 32). 64x64 tiles through LDS.
+__global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, int64_t K, int64_t N, int64_t Kp,
+                                                  unsigned short *__restrict__ Th, unsigned short *__restrict__ Tl) {
+  __shared__ float tile[64][65];
+  const int64_t n0 = int64_t(blockIdx.x) * 64, k0 = int64_t(blockIdx.y) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t k = k0 + r, n = n0 + tx;
+    tile[r][tx] = (k < K && n < N) ? A[k * N + n] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t n = n0 + r, k = k0 + tx;
+    if (n < N && k < Kp) {
+      const float x = tile[tx][r];
+      const unsigned short h = bf16_rne(x);
+      Th[n * Kp + k] = h;
+      Tl[n * Kp + k] = bf16_rne(x - bf16_to_f32(h));
+    }
+  }
+}
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// C = alpha * A^T A from the split operands, 128x128 tile per workgroup (tiles on
+// or above the diagonal, mirrored), 4 wavefronts of 64x64, K step 32, double-
+// buffered LDS. Per 16x16 block and K step: lo*hi + hi*lo + hi*hi on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the lo*lo term, below
+// 2^-16 of the product, is dropped).
+__global__ __launch_bounds__(256) void k_syrk_bf16x3(const unsigned short *__restrict__ Th,
+                                                      const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
+                                                      float *__restrict__ C, int64_t ldc, float alpha, int zero_diag,
+                                                      int nb) {
+  constexpr int BK = 32;
+  constexpr int LR = BK + 8;  // padded LDS row in bf16 elements (80 bytes)
+  __shared__ __attribute__((aligned(16))) unsigned short S[2][4][TB][LR];  // [buf][Ah Al Bh Bl][row][k]
+  int bi, bj;
+  tile_of(blockIdx.x, nb, &bi, &bj);
+  const bool diag_tile = (bi == bj);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = int64_t(bi) * TB, n0 = int64_t(bj) * TB;
+  const int narr = diag_tile ? 2 : 4;
+  float4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+  // staging: 128 rows x 4 chunks of 16 bytes per array; 2 chunks per thread
+  u16x8 st[4][2];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a >= narr) break;
+      const unsigned short *src = (a & 1) ? Tl : Th;
+      const int64_t r0 = (a < 2) ? m0 : n0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = tid + 256 * h;
+        const int row = c >> 2, part = c & 3;
+        const int64_t gr = r0 + row;
+        if (gr < N)
+          st[a][h] = *reinterpret_cast<const u16x8 *>(src + gr * Kp + kb + part * 8);
+        else
+          st[a][h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a >= narr) break;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = tid + 256 * h;
+        *reinterpret_cast<u16x8 *>(&S[buf][a][c >> 2][(c & 3) * 8]) = st[a][h];
+      }
+    }
+  };
+  int buf = 0;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int bh = diag_tile ? 0 : 2, bl = diag_tile ? 1 : 3;
+  const int kq = (lane >> 4) * 8;
+  for (int64_t kb = 0; kb < Kp; kb += BK) {
+    const bool more = kb + BK < Kp;
+    if (more) load(kb + BK);
+    bf16x8 ah[4], al[4], bhv[4], blv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + (lane & 15);
+      ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][0][r][kq]));
+      al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][1][r][kq]));
+      const int c = wn * 64 + i * 16 + (lane & 15);
+      bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bh][c][kq]));
+      blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bl][c][kq]));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
+      }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t c = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (r < N && c < N) {
+          float val = alpha * acc[i][j][v];
+          if (zero_diag && r == c) val = 0.f;
+          C[r * ldc + c] = val;
+          if (!diag_tile) C[c * ldc + r] = val;
+        }
+      }
+}
+
 // Plain VALU Gram product for FP64 values and exact integer counts:
 // 64x64 output tile, 256 threads with 4x4 outputs each, all tiles computed.
 template <typename Tin, typename Tacc, typename Tout>
@@ -213,12 +343,18 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
   int tiles = nb * (nb + 1) / 2;
   bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   if (prec == FPCA_PREC_BF16X3) {
-    if (vec)
-      hipLaunchKernelGGL((k_syrk_f32<true, 2>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
-                         int(zero_diag), nb);
-    else
-      hipLaunchKernelGGL((k_syrk_f32<false, 2>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
-                         int(zero_diag), nb);
+    const int64_t Kp = ((K + 31) / 32) * 32;
+    const size_t half = carve_bytes(size_t(N) * size_t(Kp), 2);
+    if (int rc = ws2_reserve(ctx, 2 * half)) return rc;
+    unsigned short *Th = static_cast<unsigned short *>(ctx->ws2);
+    unsigned short *Tl = reinterpret_cast<unsigned short *>(static_cast<char *>(ctx->ws2) + half);
+    if (Kp > 0) {
+      dim3 gs((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
+      hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
+      FPCA_LAUNCH_CHECK("split_t");
+    }
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3(tiles), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
+                       int(zero_diag), nb);
   } else {
     if (vec)
       hipLaunchKernelGGL((k_syrk_f32<true, 1>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,

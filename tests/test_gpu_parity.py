@@ -95,10 +95,13 @@ def test_bin_mean_parity(torch, F, h, d, M, dt):
     assert normwise_rel(host(s2), rs2) < tol
 
 
-@pytest.mark.parametrize("d,M,dt,nf", [(1, (21,), "f64", 0), (2, (9, 8), "f32", 3), (3, (5, 4, 6), "f32", 5),
-                                       (2, (16, 16), "f32", 0)])
-def test_bin_cov_parity(torch, F, h, d, M, dt, nf):
-    _say(f"bin_cov d={d} M={M} {dt} folds={nf}")
+@pytest.mark.parametrize("d,M,dt,nf,bf", [(1, (21,), "f64", 0, False), (2, (9, 8), "f32", 3, False),
+                                          (3, (5, 4, 6), "f32", 5, False), (2, (16, 16), "f32", 0, False),
+                                          (2, (9, 8), "f32", 3, True), (2, (12, 11), "f32", 0, True)])
+def test_bin_cov_parity(torch, F, h, d, M, dt, nf, bf):
+    """bf: the Gram product in BF16x3 (bf16 hi/lo split, three products, FP32
+    accumulation); its stated bound is 1e-4 normwise."""
+    _say(f"bin_cov d={d} M={M} {dt} folds={nf} bf16x3={bf}")
     rng = np.random.default_rng(200 + d)
     npdt = np.float64 if dt == "f64" else np.float32
     n = 40
@@ -111,12 +114,13 @@ def test_bin_cov_parity(torch, F, h, d, M, dt, nf):
     G = torch.empty_like(C)
     Q = torch.empty_like(C)
     cnt = torch.empty(P, P, dtype=torch.int64, device="cuda:0")
+    prec = F.FPCA_PREC_F64 if dt == "f64" else (F.FPCA_PREC_BF16X3 if bf else F.FPCA_PREC_F32)
     F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_IRREGULAR, F.FPCA_F64 if dt == "f64" else F.FPCA_F32,
-               F.FPCA_PREC_F64 if dt == "f64" else F.FPCA_PREC_F32, n, dev(torch, off), dev(torch, t),
+               prec, n, dev(torch, off), dev(torch, t),
                dev(torch, y), dev(torch, folds) if nf else None, nf, C, G, Q, None, cnt)
     h.sync()
     t64, y64 = t.astype(np.float64), y.astype(np.float64)
-    tol = 1e-12 if dt == "f64" else 1e-5
+    tol = 1e-12 if dt == "f64" else (1e-4 if bf else 1e-5)
     for s in range(ns):
         fs = -1 if s == 0 else s - 1
         rC, rG, rQ, rn = oracle.bin_cov_pairs(M, off, t64, y64, folds, fs, want_Q=True, want_cnt=True)
