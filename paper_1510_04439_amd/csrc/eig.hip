@@ -234,9 +234,12 @@ __global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restri
     Gs[e / RP][e % RP] = strided_sum(part + e, nparts, int64_t(RP) * RP);
   }
   __syncthreads();
+  // The factorization and the inverse run in wavefront 0 alone: its lanes
+  // execute in lockstep, so an LDS fence orders a write by one lane before
+  // the reads of the others.
+  if (tid >= 64) return;
   {
-    // thread i < RP owns row i; the others take part in the barriers only
-    const int i = tid;
+    const int i = tid;  // lane i < RP owns row i
     double a[RP];
 #pragma unroll
     for (int k = 0; k < RP; ++k) a[k] = i < RP ? Gs[i][k] : 0.0;
@@ -244,12 +247,12 @@ __global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restri
     for (int j = 0; j < RP; ++j) {
       const double djj = Gs[j][j];  // original diagonal
       if (i == j) col[j] = a[j];
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       const double piv = col[j];
       const bool ok = djj > 0.0 && piv > 1e-12 * djj;
       const double ljj = ok ? sqrt(piv) : 1.0;
       const double lij = (i > j && i < RP && ok) ? a[j] / ljj : 0.0;
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       if (i < RP) {
         if (i == j) {
           Ls[j][j] = ljj;
@@ -258,10 +261,10 @@ __global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restri
         if (i > j) Ls[i][j] = lij;
         col[i] = (i > j) ? lij : 0.0;
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 #pragma unroll
       for (int k = j + 1; k < RP; ++k) a[k] -= lij * col[k];
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     }
   }
   if (tid < RP) {
@@ -327,16 +330,16 @@ __global__ __launch_bounds__(256) void k_apply_rinv(int64_t P, int rp, const dou
 
 // One workgroup: B = sum of the partials restricted to the active columns,
 // symmetrized; cyclic Jacobi with round-robin ordering: the ne/2 disjoint
-// rotations of a step are applied together, B' = J^T B J and V' = V J, each
-// element computed from the previous buffer. Eigenvalues sorted descending
-// (stable); outputs the top k, their eigenvectors in the rp basis, and FVE.
-__global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const double *__restrict__ part,
-                                                  const int *__restrict__ act, int k, double *__restrict__ evals,
-                                                  double *__restrict__ fve, double *__restrict__ Uk) {
-  __shared__ double Bb[2][64][65];
-  __shared__ double Vb[2][64][65];
+// rotations of a step are applied together, B' = J^T B J and V' = V J.
+// Eigenvalues sorted descending (stable); outputs the top k, their
+// eigenvectors in the rp basis, and FVE.
+__global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double *__restrict__ part,
+                                                 const int *__restrict__ act, int k, double *__restrict__ evals,
+                                                 double *__restrict__ fve, double *__restrict__ Uk) {
+  __shared__ double Bb[1][64][65];
+  __shared__ double Vb[1][64][65];
   __shared__ double cs[32], sn[32];
-  __shared__ int partner[64], role[64], pidx[64];
+  __shared__ int pa[32], pb[32];
   __shared__ int idx[64];
   __shared__ int n_s, ne_s, stop;
   __shared__ double red_off[16], red_tot[16];
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
   }
   __syncthreads();
   const int npair = ne / 2;
-  int cur = 0;
+  const int cur = 0;
   for (int sweep = 0; sweep < 60 && ne >= 2; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < ne * ne; e += blockDim.x) {
@@ -410,29 +413,40 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rp, int nparts, const doubl
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
         }
-        partner[a] = b;
-        partner[b] = a;
-        role[a] = 0;
-        role[b] = 1;
-        pidx[a] = tid;
-        pidx[b] = tid;
+        pa[tid] = a;
+        pb[tid] = b;
         cs[tid] = c;
         sn[tid] = s;
       }
       __syncthreads();
-      const int nxt = cur ^ 1;
-      for (int e = tid; e < ne * ne; e += blockDim.x) {
-        const int i = e / ne, j = e % ne;
-        const int pi = partner[i], pj = partner[j];
-        const double ci = cs[pidx[i]], si = role[i] == 0 ? -sn[pidx[i]] : sn[pidx[i]];
-        const double cj = cs[pidx[j]], sj = role[j] == 0 ? -sn[pidx[j]] : sn[pidx[j]];
-        const double bj = Bb[cur][i][j] * cj + Bb[cur][i][pj] * sj;
-        const double bpj = Bb[cur][pi][j] * cj + Bb[cur][pi][pj] * sj;
-        Bb[nxt][i][j] = ci * bj + si * bpj;
-        Vb[nxt][i][j] = Vb[cur][i][j] * cj + Vb[cur][i][pj] * sj;
+      // In place: the 2x2 block (rows of pair m1) x (columns of pair m2) of B
+      // depends only on itself, B' = J1^T X J2 with J = [[c, s], [-s, c]];
+      // V' = V J touches the two columns of one pair in one row.
+      const int nblk = npair * npair;
+      for (int e = tid; e < nblk + ne * npair; e += blockDim.x) {
+        if (e < nblk) {
+          const int m1 = e / npair, m2 = e % npair;
+          const int a1 = pa[m1], b1 = pb[m1], a2 = pa[m2], b2 = pb[m2];
+          const double c1 = cs[m1], s1 = sn[m1], c2 = cs[m2], s2 = sn[m2];
+          const double x00 = Bb[cur][a1][a2], x01 = Bb[cur][a1][b2];
+          const double x10 = Bb[cur][b1][a2], x11 = Bb[cur][b1][b2];
+          const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
+          const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
+          Bb[cur][a1][a2] = c2 * y00 - s2 * y01;
+          Bb[cur][a1][b2] = s2 * y00 + c2 * y01;
+          Bb[cur][b1][a2] = c2 * y10 - s2 * y11;
+          Bb[cur][b1][b2] = s2 * y10 + c2 * y11;
+        } else {
+          const int f = e - nblk;
+          const int row = f / npair, m = f % npair;
+          const int a = pa[m], b = pb[m];
+          const double c = cs[m], s = sn[m];
+          const double va = Vb[cur][row][a], vb = Vb[cur][row][b];
+          Vb[cur][row][a] = c * va - s * vb;
+          Vb[cur][row][b] = s * va + c * vb;
+        }
       }
       __syncthreads();
-      cur = nxt;
     }
   }
   __shared__ int order[64];
@@ -670,7 +684,7 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
     if (int rc = cholqr2()) return rc;
   }
   if (int rc = product(Z, 2)) return rc;  // Z = A Q and the partials of Q^T Z
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, ctx->stream, rp, int(ngram), gpart, act, k, ev_d, fve_d, Uk);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, ctx->stream, rp, int(ngram), gpart, act, k, ev_d, fve_d, Uk);
   FPCA_LAUNCH_CHECK("jacobi");
   hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, rp, k, Q, Uk, w, phi, red);
   FPCA_LAUNCH_CHECK("phi");

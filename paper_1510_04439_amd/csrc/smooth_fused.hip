@@ -93,84 +93,112 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
 // U layout: NU arrays of P x P (row s, column t). Array order:
 //   0 G00, 1 G10, 2 G01, [3 C00, 4 C10, 5 C01, 6 C20, 7 C11, 8 C02]
 // (exponents of u in (t1, t2)).
-template <bool ANALYTIC>
+template <bool ANALYTIC, int R>
 __global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, const float *__restrict__ C,
-                                                  const float *__restrict__ G, Taps tp, int R,
-                                                  float *__restrict__ U) {
+                                                  const float *__restrict__ G, Taps tp, float *__restrict__ U) {
   constexpr int NA = ANALYTIC ? 2 : 5;  // t2-pass arrays: GK GU [CK CU CUU]
+  constexpr int NB = 4;                 // consecutive outputs per thread
+  constexpr int WIN = NB + 2 * R;
   extern __shared__ float lds[];
-  float *rowG = lds;                  // P
-  float *rowC = lds + P;              // P (general only)
-  float *A = lds + (ANALYTIC ? 1 : 2) * P;  // NA x P
+  const int LD = M2 + 1;  // padded t-plane row: both passes are bank-conflict free
+  const int plane = M1 * LD;
+  float *rowG = lds;
+  float *rowC = lds + plane;
+  float *A = lds + (ANALYTIC ? 1 : 2) * plane;  // NA planes
   const int64_t s = blockIdx.x;
-  const float *g = G + s * P;
-  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
-    rowG[e] = g[e];
-    if (!ANALYTIC) rowC[e] = C[s * P + e];
-  }
-  __syncthreads();
-  // t2 pass (contiguous coordinate)
-  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < P; e += blockDim.x) {
     const int t1 = int(e / M2), t2 = int(e % M2);
-    const int lo = -min(R, t2), hi = min(R, M2 - 1 - t2);
-    float gk = 0.f, gu = 0.f, ck = 0.f, cu = 0.f, cuu = 0.f;
-    for (int m = lo; m <= hi; ++m) {
-      const float k0 = tp.k[0][m + R], k1 = tp.k[1][m + R];
-      const float vg = rowG[e + m];
-      gk = fmaf(k0, vg, gk);
-      gu = fmaf(k1, vg, gu);
-      if (!ANALYTIC) {
-        const float vc = rowC[e + m];
-        ck = fmaf(k0, vc, ck);
-        cu = fmaf(k1, vc, cu);
-        cuu = fmaf(tp.k[2][m + R], vc, cuu);
-      }
+    rowG[t1 * LD + t2] = G[s * P + e];
+    if (!ANALYTIC) rowC[t1 * LD + t2] = C[s * P + e];
+  }
+  __syncthreads();
+  // t2 pass: thread -> (strip of NB outputs along t2, line t1), t1 fastest
+  const int nst2 = (M2 + NB - 1) / NB;
+  for (int sidx = tid; sidx < nst2 * M1; sidx += blockDim.x) {
+    const int t1 = sidx % M1, t20 = (sidx / M1) * NB;
+    float wg[WIN], wc[WIN];
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) {
+      const int t2 = t20 - R + i;
+      const bool in = t2 >= 0 && t2 < M2;
+      wg[i] = in ? rowG[t1 * LD + t2] : 0.f;
+      if (!ANALYTIC) wc[i] = in ? rowC[t1 * LD + t2] : 0.f;
     }
-    (void)t1;
-    A[0 * P + e] = gk;
-    A[1 * P + e] = gu;
-    if (!ANALYTIC) {
-      A[2 * P + e] = ck;
-      A[3 * P + e] = cu;
-      A[4 * P + e] = cuu;
+#pragma unroll
+    for (int o = 0; o < NB; ++o) {
+      float gk = 0.f, gu = 0.f, ck = 0.f, cu = 0.f, cuu = 0.f;
+#pragma unroll
+      for (int m = 0; m <= 2 * R; ++m) {
+        gk = fmaf(tp.k[0][m], wg[o + m], gk);
+        gu = fmaf(tp.k[1][m], wg[o + m], gu);
+        if (!ANALYTIC) {
+          ck = fmaf(tp.k[0][m], wc[o + m], ck);
+          cu = fmaf(tp.k[1][m], wc[o + m], cu);
+          cuu = fmaf(tp.k[2][m], wc[o + m], cuu);
+        }
+      }
+      if (t20 + o < M2) {
+        const int e = t1 * LD + t20 + o;
+        A[0 * plane + e] = gk;
+        A[1 * plane + e] = gu;
+        if (!ANALYTIC) {
+          A[2 * plane + e] = ck;
+          A[3 * plane + e] = cu;
+          A[4 * plane + e] = cuu;
+        }
+      }
     }
   }
   __syncthreads();
-  // t1 pass (stride M2), written to HBM row s
+  // t1 pass: thread -> (t2, strip of NB outputs along t1), t2 fastest; results to HBM row s
   const int64_t PP = P * P;
-  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
-    const int t1 = int(e / M2);
-    const int lo = -min(R, t1), hi = min(R, M1 - 1 - t1);
-    float g00 = 0.f, g10 = 0.f, g01 = 0.f;
-    float c00 = 0.f, c10 = 0.f, c20 = 0.f, c01 = 0.f, c11 = 0.f, c02 = 0.f;
-    for (int m = lo; m <= hi; ++m) {
-      const float k0 = tp.k[0][m + R], k1 = tp.k[1][m + R];
-      const int64_t o = e + int64_t(m) * M2;
-      const float gk = A[0 * P + o], gu = A[1 * P + o];
-      g00 = fmaf(k0, gk, g00);
-      g10 = fmaf(k1, gk, g10);
-      g01 = fmaf(k0, gu, g01);
-      if (!ANALYTIC) {
-        const float ck = A[2 * P + o], cu = A[3 * P + o], cuu = A[4 * P + o];
-        c00 = fmaf(k0, ck, c00);
-        c10 = fmaf(k1, ck, c10);
-        c20 = fmaf(tp.k[2][m + R], ck, c20);
-        c01 = fmaf(k0, cu, c01);
-        c11 = fmaf(k1, cu, c11);
-        c02 = fmaf(k0, cuu, c02);
+  const int nst1 = (M1 + NB - 1) / NB;
+  for (int sidx = tid; sidx < nst1 * M2; sidx += blockDim.x) {
+    const int t2 = sidx % M2, t10 = (sidx / M2) * NB;
+    float out[ANALYTIC ? 3 : 9][NB];
+#pragma unroll
+    for (int q = 0; q < (ANALYTIC ? 3 : 9); ++q)
+#pragma unroll
+      for (int o = 0; o < NB; ++o) out[q][o] = 0.f;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      float w[WIN];
+#pragma unroll
+      for (int i = 0; i < WIN; ++i) {
+        const int t1 = t10 - R + i;
+        w[i] = (t1 >= 0 && t1 < M1) ? A[a * plane + t1 * LD + t2] : 0.f;
       }
+#pragma unroll
+      for (int o = 0; o < NB; ++o)
+#pragma unroll
+        for (int m = 0; m <= 2 * R; ++m) {
+          const float v = w[o + m];
+          // t2-pass array a -> outputs (t1 exponent): GK->G00,G10; GU->G01;
+          // CK->C00,C10,C20; CU->C01,C11; CUU->C02
+          if (a == 0) {
+            out[0][o] = fmaf(tp.k[0][m], v, out[0][o]);
+            out[1][o] = fmaf(tp.k[1][m], v, out[1][o]);
+          } else if (a == 1) {
+            out[2][o] = fmaf(tp.k[0][m], v, out[2][o]);
+          } else if (a == 2) {
+            out[3][o] = fmaf(tp.k[0][m], v, out[3][o]);
+            out[4][o] = fmaf(tp.k[1][m], v, out[4][o]);
+            out[6][o] = fmaf(tp.k[2][m], v, out[6][o]);
+          } else if (a == 3) {
+            out[5][o] = fmaf(tp.k[0][m], v, out[5][o]);
+            out[7][o] = fmaf(tp.k[1][m], v, out[7][o]);
+          } else {
+            out[8][o] = fmaf(tp.k[0][m], v, out[8][o]);
+          }
+        }
     }
-    float *u = U + s * P + e;
-    u[0 * PP] = g00;
-    u[1 * PP] = g10;
-    u[2 * PP] = g01;
-    if (!ANALYTIC) {
-      u[3 * PP] = c00;
-      u[4 * PP] = c10;
-      u[5 * PP] = c01;
-      u[6 * PP] = c20;
-      u[7 * PP] = c11;
-      u[8 * PP] = c02;
+#pragma unroll
+    for (int o = 0; o < NB; ++o) {
+      if (t10 + o >= M1) continue;
+      float *u = U + s * P + int64_t(t10 + o) * M2 + t2;
+#pragma unroll
+      for (int q = 0; q < (ANALYTIC ? 3 : 9); ++q) u[q * PP] = out[q][o];
     }
   }
 }
@@ -268,17 +296,24 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
 #pragma unroll
     for (int i = 0; i < W; ++i) win[a][i] = 0.f;
 
-  const int nload = NU * 64 * TW;
+  // Each thread stages NU values per row (64 s2 x TW t per array, 512 threads);
+  // the next row is fetched into registers while the current one is used.
+  static_assert(64 * TW == 512, "one staged value per thread and array");
+  const int ls2 = tid / TW, ltt = tid % TW;
+  const bool lok = ls2 < M2 && t0 + ltt < P;
+  float pre[NU];
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a)
+      pre[a] = (r < M1 && lok) ? U[a * PP + (int64_t(r) * M2 + ls2) * P + t0 + ltt] : 0.f;
+  };
+  fetch(0);
   for (int r = 0; r <= xmax + R; ++r) {
     const int buf = r & 1;
-    for (int e = tid; e < nload; e += 512) {
-      const int a = e / (64 * TW), rem = e % (64 * TW);
-      const int s2 = rem / TW, tt = rem % TW;
-      float v = 0.f;
-      if (r < M1 && s2 < M2 && t0 + tt < P) v = U[a * PP + (int64_t(r) * M2 + s2) * P + t0 + tt];
-      stage[buf][a][s2][tt] = v;
-    }
+#pragma unroll
+    for (int a = 0; a < NU; ++a) stage[buf][a][ls2][ltt] = pre[a];
     __syncthreads();
+    if (r < xmax + R) fetch(r + 1);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
 #pragma unroll
@@ -420,18 +455,32 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C
     tab.W = Wt;
     tab.Dg = Dt;
   }
-  const size_t lds_t = size_t((analytic ? 1 : 2) + (analytic ? 2 : 5)) * P * sizeof(float);
-  if (analytic) {
-    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));
-  } else {
-    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));
+  const size_t lds_t = size_t((analytic ? 1 : 2) + (analytic ? 2 : 5)) * size_t(M1) * (M2 + 1) * sizeof(float);
+#define STAGE_T(A, RR)                                                                                        \
+  do {                                                                                                        \
+    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<A, RR>),                          \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));                    \
+    hipLaunchKernelGGL((k_stage_t<A, RR>), dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, \
+                       tp, U);                                                                                \
+  } while (0)
+#define STAGE_T_R(A)               \
+  switch (R) {                     \
+    case 1: STAGE_T(A, 1); break;  \
+    case 2: STAGE_T(A, 2); break;  \
+    case 3: STAGE_T(A, 3); break;  \
+    case 4: STAGE_T(A, 4); break;  \
+    case 5: STAGE_T(A, 5); break;  \
+    case 6: STAGE_T(A, 6); break;  \
+    case 7: STAGE_T(A, 7); break;  \
+    default: STAGE_T(A, 8); break; \
   }
-  if (analytic)
-    hipLaunchKernelGGL(k_stage_t<true>, dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, tp, R, U);
-  else
-    hipLaunchKernelGGL(k_stage_t<false>, dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, tp, R, U);
+  if (analytic) {
+    STAGE_T_R(true)
+  } else {
+    STAGE_T_R(false)
+  }
+#undef STAGE_T_R
+#undef STAGE_T
   FPCA_LAUNCH_CHECK("stage_t");
   const int nchunks = int((P + TW - 1) / TW);
   const int nlines = (nchunks + 3) / 4;
