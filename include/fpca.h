@@ -197,6 +197,23 @@ int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid
                         const void *gamma, const double *quad_w, int k, int oversample,
                         int power_iters, uint64_t seed, double *evals, void *efuns, double *fve);
 
+/*
+ * fpca_cv_batched -- bandwidth selection for the covariance smoother by
+ * leave-curves-out cross-validation (the CV idea of Section 3.3, on folds of
+ * curves and binned data). For every bandwidth h (row of `bandwidths`) and
+ * fold f, the smoother of eq. 2.4 is fitted to the pairs of the curves outside
+ * fold f, C - C_f and G - G_f, giving Ghat; the held-out pairs are scored
+ * through their bins:
+ *   scores[h * n_folds + f] = sum_{p,q} Q_f - 2 G_f Ghat + C_f Ghat^2
+ * (= sum over held-out pairs of w (Y_ij Y_il - Ghat)^2 spread over the pair's
+ * bins; Ghat is taken as 0 where the window is empty), accumulated in FP64.
+ *   C, G, Q: (n_folds+1) x P x P device arrays from fpca_bin(kind = COV) with
+ *     folds and sq_sums (slab 0 all curves, slab f+1 fold f).
+ *   bandwidths: host, n_h x d. scores: host, n_h x n_folds. Synchronizes.
+ */
+int fpca_cv_batched(fpca_handle handle, const fpca_grid *grid, int dtype, int n_folds, const void *C,
+                    const void *G, const void *Q, int n_h, const double *bandwidths, double *scores);
+
 /* Standard normal numbers 0..count-1 of stream `seed` (the test-matrix
  * generator above), FP64, into the device array out. */
 int fpca_rng_normal(fpca_handle handle, uint64_t seed, int64_t count, double *out);

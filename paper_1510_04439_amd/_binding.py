@@ -31,6 +31,7 @@ FPCA_K_EPANECHNIKOV = 0
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
+    "fpca_cv_batched",
 ]
 
 
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_double), vp,
                                       ctypes.POINTER(ctypes.c_double)]
     L.fpca_rng_normal.argtypes = [vp, u64, i64, vp]
+    L.fpca_cv_batched.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, vp, vp, vp, i32,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
 
@@ -188,3 +191,18 @@ def fpca_eig_randomized(h: Handle, dtype: int, prec: int, grid: Grid, gamma, qua
 def fpca_rng_normal(h: Handle, seed: int, count: int, out):
     _check(load_library().fpca_rng_normal(h.ptr, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(count),
                                           _ptr(out)))
+
+
+def fpca_cv_batched(h: Handle, grid: Grid, dtype: int, n_folds: int, C, G, Q, bandwidths):
+    """bandwidths: n_h x d (or n_h scalars shared by all coordinates). Returns scores (n_h x n_folds)."""
+    bw = np.asarray(bandwidths, np.float64)
+    if bw.ndim == 1:
+        bw = np.repeat(bw[:, None], grid.d, axis=1)
+    bw = np.ascontiguousarray(bw)
+    n_h = bw.shape[0]
+    out = np.zeros(n_h * n_folds)
+    g = grid.c()
+    _check(load_library().fpca_cv_batched(h.ptr, ctypes.byref(g), dtype, int(n_folds), _ptr(C), _ptr(G), _ptr(Q),
+                                          n_h, bw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(n_h, n_folds)

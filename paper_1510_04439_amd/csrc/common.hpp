@@ -21,6 +21,10 @@ struct fpca_context {
   // may live in the first arena).
   void *ws2 = nullptr;
   size_t ws2_size = 0;
+  // Third arena for the cross-validation buffers (the smoother it calls uses
+  // the first).
+  void *ws3 = nullptr;
+  size_t ws3_size = 0;
   // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
   int *d_flags = nullptr;
   int *h_flags = nullptr;  // pinned mirror
@@ -47,6 +51,11 @@ int hip_fail(hipError_t e, const char *what);
 // Scratch arenas: ensure at least `bytes`; returns FPCA_OK or an error.
 int ws_reserve(fpca_context *ctx, size_t bytes);
 int ws2_reserve(fpca_context *ctx, size_t bytes);
+int ws3_reserve(fpca_context *ctx, size_t bytes);
+
+// Covariance smoother behind fpca_smooth_cov (arguments already validated).
+int smooth_cov_internal(fpca_context *ctx, const fpca_grid *grid, int dtype, const void *C, double c_uniform,
+                        const void *G, const void *mu, const double *bw, void *gamma, int8_t *status);
 
 // Bump allocator over the reserved arena (256-byte aligned carving).
 struct Carver {

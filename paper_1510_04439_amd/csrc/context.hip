@@ -87,25 +87,28 @@ int ws_reserve(fpca_context *ctx, size_t bytes) {
   return FPCA_OK;
 }
 
-int ws2_reserve(fpca_context *ctx, size_t bytes) {
-  if (bytes <= ctx->ws2_size) return FPCA_OK;
-  if (ctx->ws_limit && bytes + ctx->ws_size > ctx->ws_limit)
+static int arena_reserve(fpca_context *ctx, void **arena, size_t *size, size_t bytes) {
+  if (bytes <= *size) return FPCA_OK;
+  if (ctx->ws_limit && bytes > ctx->ws_limit)
     return set_error(FPCA_ERR_WORKSPACE, "scratch request %zu bytes exceeds the limit %zu", bytes, ctx->ws_limit);
-  if (ctx->ws2) {
+  if (*arena) {
     FPCA_HIP(hipStreamSynchronize(ctx->stream));
-    FPCA_HIP(hipFree(ctx->ws2));
-    ctx->ws2 = nullptr;
-    ctx->ws2_size = 0;
+    FPCA_HIP(hipFree(*arena));
+    *arena = nullptr;
+    *size = 0;
   }
-  hipError_t e = hipMalloc(&ctx->ws2, bytes);
+  hipError_t e = hipMalloc(arena, bytes);
   if (e != hipSuccess) {
-    ctx->ws2 = nullptr;
+    *arena = nullptr;
     (void)hipGetLastError();
     return set_error(FPCA_ERR_WORKSPACE, "hipMalloc of %zu scratch bytes failed: %s", bytes, hipGetErrorString(e));
   }
-  ctx->ws2_size = bytes;
+  *size = bytes;
   return FPCA_OK;
 }
+
+int ws2_reserve(fpca_context *ctx, size_t bytes) { return arena_reserve(ctx, &ctx->ws2, &ctx->ws2_size, bytes); }
+int ws3_reserve(fpca_context *ctx, size_t bytes) { return arena_reserve(ctx, &ctx->ws3, &ctx->ws3_size, bytes); }
 
 template <typename T>
 __global__ void k_fill(T *__restrict__ p, T v, int64_t n) {
@@ -173,6 +176,7 @@ int fpca_destroy(fpca_handle ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ws2) (void)hipFree(ctx->ws2);
+  if (ctx->ws3) (void)hipFree(ctx->ws3);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   delete ctx;

@@ -355,6 +355,11 @@ extern "C" int fpca_smooth_cov(fpca_handle ctx, const fpca_grid *grid, int dtype
   if (P > (int64_t(1) << 15)) return set_error(FPCA_ERR_UNSUPPORTED, "covariance grid too large (P=%lld)", (long long)P);
   if (int rc = check_bw(bandwidth, grid->d)) return rc;
   if (int rc = set_device(ctx)) return rc;
+  return smooth_cov_internal(ctx, grid, dtype, C, c_uniform, G, mu, bandwidth, gamma, status);
+}
+
+int fpca::smooth_cov_internal(fpca_context *ctx, const fpca_grid *grid, int dtype, const void *C, double c_uniform,
+                              const void *G, const void *mu, const double *bandwidth, void *gamma, int8_t *status) {
   if (dtype == FPCA_F64)
     return smooth_cov_impl<double>(ctx, grid, static_cast<const double *>(C), c_uniform,
                                    static_cast<const double *>(G), static_cast<const double *>(mu), bandwidth,

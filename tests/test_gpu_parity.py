@@ -293,6 +293,33 @@ def test_smooth_cov_analytic_common_grid(torch, F, h, M, hb):
                           torch.empty(P, P, dtype=torch.float32, device="cuda:0"))
 
 
+# ------------------------------------------------------------------ batched CV
+@pytest.mark.parametrize("M,nf,hs", [((7, 6), 3, [0.2, 0.35, 0.6]), ((4, 5, 4), 5, [0.3, 0.55]),
+                                     ((12, 12), 4, [0.1, 0.25])])
+def test_cv_batched_parity(torch, F, h, M, nf, hs):
+    """Scores of every (bandwidth, fold) job against the oracle: smoother on the
+    other folds' pairs (full grid), then sum [Q_f - 2 G_f Ghat + C_f Ghat^2]."""
+    _say(f"cv M={M} folds={nf} h={hs}")
+    rng = np.random.default_rng(40 + len(M))
+    d = len(M)
+    n = 30
+    off, t, y = rand_irregular(rng, d, n, 1, 14, np.float32)
+    folds = fold_assignment(n, nf, seed=9)
+    P = int(np.prod(M))
+    t64, y64 = t.astype(np.float64), y.astype(np.float64)
+    slabs = [oracle.bin_cov_pairs(M, off, t64, y64, folds, fs, want_Q=True) for fs in [-1] + list(range(nf))]
+    Ch, Gh, Qh = (np.stack([s[i] for s in slabs]).astype(np.float32).astype(np.float64) for i in range(3))
+    C, G, Q = (dev(torch, a.astype(np.float32)) for a in (Ch, Gh, Qh))
+    scores = F.fpca_cv_batched(h, F.Grid(M), F.FPCA_F32, nf, C, G, Q, hs)
+    ref = np.zeros((len(hs), nf))
+    for i, hb in enumerate(hs):
+        for f in range(nf):
+            b, st = oracle.smooth_cov_raw(M, hb, Ch[0] - Ch[f + 1], Gh[0] - Gh[f + 1])
+            Ghat = oracle.assemble_cov(b.reshape(P, P), np.zeros(P))
+            ref[i, f] = oracle.cv_score(Qh[f + 1], Gh[f + 1], Ch[f + 1], Ghat)
+    np.testing.assert_allclose(scores, ref, rtol=1e-5)
+
+
 # ------------------------------------------------------------------ eigen
 def test_eig_closed_form_and_oracle(torch, F, h):
     _say("eig closed form")
