@@ -214,6 +214,44 @@ int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid
 int fpca_cv_batched(fpca_handle handle, const fpca_grid *grid, int dtype, int n_folds, const void *C,
                     const void *G, const void *Q, int n_h, const double *bandwidths, double *scores);
 
+/*
+ * Bandwidth surrogate (an addition to the paper's method, whose Section 3.3
+ * selects bandwidths by CV with a trust-region search): a small MLP maps 32
+ * summary features of the binned arrays to log h of the covariance smoother.
+ * It is trained on datasets labelled by fpca_cv_batched, which remains the
+ * fallback. FP32 throughout.
+ *
+ * fpca_bw_features: features of one dataset (FP32 binned arrays of this
+ *   library): curve-size statistics from offsets[n+1]; mean-bin statistics
+ *   from c, s, s2 (P; s2 = sq_sums of MEAN binning, may be NULL); pair-weight
+ *   density, lag-0 raw product, noise fraction and raw-product variogram at
+ *   lags 1..8 along the first and last coordinates from C, G (P x P) and Q
+ *   (sq_sums of COV binning, may be NULL). feat: device, 32 floats.
+ * fpca_bw_num_params: number of MLP parameters (20865), laid out as
+ *   W1[128][32] b1[128] W2[128][128] b2[128] W3[128] b3[1].
+ * fpca_bw_mlp_forward: out[b] = W3 gelu(W2 gelu(W1 x_b + b1) + b2) + b3 with
+ *   x_b = (feat[b] - feat_mean) / feat_sd and the exact GELU z Phi(z); z1, z2
+ *   (batch x 128 each, optional together) receive the pre-activations.
+ * fpca_bw_mlp_backward: gradient of mean_b (out[b] - target[b])^2 with
+ *   respect to the parameters, from the forward pass's out, z1, z2; work is a
+ *   device scratch of batch*(2*128+1) floats; grad has fpca_bw_num_params()
+ *   floats. Deterministic (fixed summation order).
+ * fpca_bw_adam_step: one Adam update (step >= 1 counts updates) with
+ *   decoupled weight decay; m and v are the moment buffers.
+ */
+int fpca_bw_features(fpca_handle handle, const fpca_grid *grid, int64_t n, const int64_t *offsets,
+                     const float *c, const float *s, const float *s2, const float *C, const float *G,
+                     const float *Q, float *feat);
+int fpca_bw_num_params(void);
+int fpca_bw_mlp_forward(fpca_handle handle, int batch, const float *feat, const float *feat_mean,
+                        const float *feat_sd, const float *params, float *out, float *z1, float *z2);
+int fpca_bw_mlp_backward(fpca_handle handle, int batch, const float *feat, const float *feat_mean,
+                         const float *feat_sd, const float *params, const float *out,
+                         const float *target, const float *z1, const float *z2, float *work,
+                         float *grad);
+int fpca_bw_adam_step(fpca_handle handle, int step, float lr, float beta1, float beta2, float eps,
+                      float weight_decay, float *params, const float *grad, float *m, float *v);
+
 /* Standard normal numbers 0..count-1 of stream `seed` (the test-matrix
  * generator above), FP64, into the device array out. */
 int fpca_rng_normal(fpca_handle handle, uint64_t seed, int64_t count, double *out);

@@ -31,7 +31,8 @@ FPCA_K_EPANECHNIKOV = 0
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
-    "fpca_cv_batched",
+    "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
+    "fpca_bw_mlp_backward", "fpca_bw_adam_step",
 ]
 
 
@@ -74,6 +75,12 @@ def load_library(path: str = LIB_PATH):
     L.fpca_rng_normal.argtypes = [vp, u64, i64, vp]
     L.fpca_cv_batched.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, vp, vp, vp, i32,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.fpca_bw_features.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fpca_bw_num_params.argtypes = []
+    L.fpca_bw_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.fpca_bw_mlp_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    f32 = ctypes.c_float
+    L.fpca_bw_adam_step.argtypes = [vp, i32, f32, f32, f32, f32, f32, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -191,6 +198,34 @@ def fpca_eig_randomized(h: Handle, dtype: int, prec: int, grid: Grid, gamma, qua
 def fpca_rng_normal(h: Handle, seed: int, count: int, out):
     _check(load_library().fpca_rng_normal(h.ptr, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(count),
                                           _ptr(out)))
+
+
+def fpca_bw_features(h: Handle, grid: Grid, n: int, offsets, c, s, s2, C, G, Q, feat):
+    g = grid.c()
+    _check(load_library().fpca_bw_features(h.ptr, ctypes.byref(g), int(n), _ptr(offsets), _ptr(c), _ptr(s),
+                                           _ptr(s2), _ptr(C), _ptr(G), _ptr(Q), _ptr(feat)))
+
+
+def fpca_bw_num_params() -> int:
+    return int(load_library().fpca_bw_num_params())
+
+
+def fpca_bw_mlp_forward(h: Handle, batch: int, feat, feat_mean, feat_sd, params, out, z1=None, z2=None):
+    _check(load_library().fpca_bw_mlp_forward(h.ptr, int(batch), _ptr(feat), _ptr(feat_mean), _ptr(feat_sd),
+                                              _ptr(params), _ptr(out), _ptr(z1), _ptr(z2)))
+
+
+def fpca_bw_mlp_backward(h: Handle, batch: int, feat, feat_mean, feat_sd, params, out, target, z1, z2, work,
+                         grad):
+    _check(load_library().fpca_bw_mlp_backward(h.ptr, int(batch), _ptr(feat), _ptr(feat_mean), _ptr(feat_sd),
+                                               _ptr(params), _ptr(out), _ptr(target), _ptr(z1), _ptr(z2),
+                                               _ptr(work), _ptr(grad)))
+
+
+def fpca_bw_adam_step(h: Handle, step: int, lr: float, beta1: float, beta2: float, eps: float,
+                      weight_decay: float, params, grad, m, v):
+    _check(load_library().fpca_bw_adam_step(h.ptr, int(step), lr, beta1, beta2, eps, weight_decay, _ptr(params),
+                                            _ptr(grad), _ptr(m), _ptr(v)))
 
 
 def fpca_cv_batched(h: Handle, grid: Grid, dtype: int, n_folds: int, C, G, Q, bandwidths):

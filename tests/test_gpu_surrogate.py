@@ -1,0 +1,96 @@
+"""GPU parity of the bandwidth-surrogate kernels against the FP64 reference:
+features (1e-5 relative, 1e-6 absolute), MLP forward (1e-5), backward (1e-4
+normwise), Adam (1e-6)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+from tests._util import normwise_rel, rand_irregular
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a GPU"
+    return T
+
+
+@pytest.fixture(scope="module")
+def F(torch):
+    import paper_1510_04439_amd as F
+    F.load_library()
+    return F
+
+
+@pytest.fixture(scope="module")
+def h(F):
+    hh = F.Handle(0)
+    yield hh
+    hh.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_num_params(F):
+    assert F.fpca_bw_num_params() == ref.NPARAM == 20865
+
+
+@pytest.mark.parametrize("M", [(7, 6), (5, 4, 4)])
+def test_features_parity(torch, F, h, M):
+    print(f"features M={M}", flush=True)
+    rng = np.random.default_rng(3)
+    d = len(M)
+    off, t, y = rand_irregular(rng, d, 40, 2, 20, np.float32)
+    t64, y64 = t.astype(np.float64), y.astype(np.float64)
+    c, s, _, _ = oracle.bin_mean(M, off, t64, y64)
+    _, s2, _, _ = oracle.bin_mean(M, off, t64, y64 ** 2)
+    C, G, Q = oracle.bin_cov_pairs(M, off, t64, y64, want_Q=True)
+    arrs = [a.astype(np.float32) for a in (c, s, s2, C, G, Q)]
+    feat = torch.empty(32, dtype=torch.float32, device="cuda:0")
+    F.fpca_bw_features(h, F.Grid(M), len(off) - 1, dev(torch, off), *[dev(torch, a) for a in arrs], feat)
+    got = feat.cpu().numpy().astype(np.float64)
+    want = ref.features(M, off, *[a.astype(np.float64) for a in arrs])
+    np.testing.assert_allclose(got, want, rtol=1e-4, atol=1e-5)
+
+
+def test_mlp_forward_backward_adam(torch, F, h):
+    print("mlp", flush=True)
+    rng = np.random.default_rng(5)
+    B = 37
+    theta = (rng.standard_normal(ref.NPARAM) * 0.1).astype(np.float32)
+    feat = rng.standard_normal((B, 32)).astype(np.float32) * 3 + 1
+    fmu = rng.standard_normal(32).astype(np.float32)
+    fsd = (rng.random(32) + 0.5).astype(np.float32)
+    target = rng.standard_normal(B).astype(np.float32)
+    X = (feat.astype(np.float64) - fmu) / fsd
+    out_ref, _ = ref.forward(theta.astype(np.float64), X)
+    loss_ref, g_ref = ref.loss_and_grad(theta.astype(np.float64), X, target.astype(np.float64))
+    T = lambda a: dev(torch, a)
+    prm, ft, mu_t, sd_t, tg = T(theta), T(feat), T(fmu), T(fsd), T(target)
+    out = torch.empty(B, dtype=torch.float32, device="cuda:0")
+    z1 = torch.empty(B, 128, dtype=torch.float32, device="cuda:0")
+    z2 = torch.empty_like(z1)
+    F.fpca_bw_mlp_forward(h, B, ft, mu_t, sd_t, prm, out, z1, z2)
+    o = out.cpu().numpy()
+    assert np.abs(o - out_ref).max() <= 1e-5 * max(1.0, np.abs(out_ref).max())
+    work = torch.empty(B * 257, dtype=torch.float32, device="cuda:0")
+    grad = torch.empty(ref.NPARAM, dtype=torch.float32, device="cuda:0")
+    F.fpca_bw_mlp_backward(h, B, ft, mu_t, sd_t, prm, out, tg, z1, z2, work, grad)
+    g = grad.cpu().numpy()
+    assert normwise_rel(g, g_ref) < 1e-4
+    m = torch.zeros_like(grad)
+    v = torch.zeros_like(grad)
+    th_ref, m_ref, v_ref = theta.astype(np.float64), np.zeros(ref.NPARAM), np.zeros(ref.NPARAM)
+    gg = g.astype(np.float64)
+    for step in (1, 2, 3):
+        F.fpca_bw_adam_step(h, step, 1e-3, 0.9, 0.999, 1e-8, 1e-4, prm, grad, m, v)
+        th_ref, m_ref, v_ref = ref.adam_step(th_ref, gg, m_ref, v_ref, step, 1e-3, wd=1e-4)
+    torch.cuda.synchronize()
+    assert np.abs(prm.cpu().numpy() - th_ref).max() < 1e-6

@@ -402,3 +402,53 @@ def test_binned_cv_equals_pairwise_on_nodes():
                 if j != l:
                     direct += w * (y[j] * y[l] - Ghat[node[j], node[l]]) ** 2
     assert abs(score - direct) < 1e-12 * abs(direct)
+
+
+# ------------------------------------------------------------------ P13 surrogate reference
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(21)
+    theta = rng.standard_normal(mlp.NPARAM) * 0.1
+    X = rng.standard_normal((7, mlp.NF))
+    y = rng.standard_normal(7)
+    loss, g = mlp.loss_and_grad(theta, X, y)
+    idx = rng.choice(mlp.NPARAM, 60, replace=False)
+    idx = np.concatenate([idx, [mlp.NPARAM - 1, 0, 4096, 4096 + 128]])
+    eps = 1e-6
+    for i in idx:
+        tp = theta.copy(); tp[i] += eps
+        tm = theta.copy(); tm[i] -= eps
+        fd = (mlp.loss_and_grad(tp, X, y)[0] - mlp.loss_and_grad(tm, X, y)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    """Bias-corrected Adam moves each parameter by lr * sign(g) at step 1."""
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    th = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    th2, m, v = mlp.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3, eps=1e-12)
+    np.testing.assert_allclose(th - th2, 1e-3 * np.sign(g), rtol=1e-9)
+
+
+def test_features_lag_structure_and_counts():
+    """Pair arrays with G = rho^lag C along each coordinate give variogram
+    features rho^l; curve-size features equal their definitions."""
+    from oracle import mlp
+    M = (6, 5)
+    P = 30
+    coords = np.stack(np.unravel_index(np.arange(P), M), axis=1)
+    diff = np.abs(coords[:, None, :] - coords[None, :, :])
+    C = 1.0 + 0.1 * (coords[:, None, 0] + coords[None, :, 1])
+    rho = 0.7
+    G = C * rho ** diff.sum(-1) * 2.0
+    off = np.array([0, 3, 7, 12], np.int64)
+    c = np.ones(P)
+    s = np.full(P, 0.5)
+    s2 = np.full(P, 3.0)
+    f = mlp.features(M, off, c, s, s2, C, G)
+    assert abs(f[0] - np.log(3)) < 1e-15 and abs(f[2] - np.log(3 * 2 + 4 * 3 + 5 * 4)) < 1e-15
+    np.testing.assert_allclose(f[12:12 + 5], rho ** np.arange(1, 6), rtol=1e-12)
+    np.testing.assert_allclose(f[20:20 + 4], rho ** np.arange(1, 5), rtol=1e-12)
+    assert abs(f[9] - np.log(2.0)) < 1e-12 and abs(f[10] - (3.0 - 2.0) / 3.0) < 1e-12
