@@ -63,6 +63,39 @@ def cpu_baseline(ds, G_host: np.ndarray, budget_s: float = 15.0):
                       f"of the raw surface (binning and eigendecomposition not included), {t_used:.1f} s"}
 
 
+def hselect_timing(h, torch, n_datasets: int = 5):
+    """Bandwidth selection on held-out d=2 irregular datasets of the surrogate
+    family (32x32 grid, 16 bandwidths x 5 folds): the trained surrogate
+    (features + MLP) against batched CV, both after the shared binning."""
+    from paper_1510_04439_amd import surrogate as S
+    from fpca_synth import make_surrogate_dataset
+    if not os.path.exists(S.MODEL_PATH):
+        return None
+    log("bandwidth selection: surrogate vs batched CV")
+    model = S.Surrogate.load()
+    rows = []
+    for i in range(n_datasets):
+        ds = make_surrogate_dataset(i, "test")
+        bd = S.bin_dataset(h, ds)
+        S.cv_scores(h, bd, S.H_GRID[:1])  # warm the smoother's scratch
+        model.select(h, bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hs, fb = model.select(h, bd)
+        torch.cuda.synchronize()
+        t_sur = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sc = S.cv_scores(h, bd, S.H_GRID)
+        t_cv = time.perf_counter() - t0
+        s_sur = float(S.cv_scores(h, bd, [hs])[0])
+        rows.append((t_sur, t_cv, s_sur / float(sc.min()), fb))
+    t_sur = float(np.median([r[0] for r in rows]))
+    t_cv = float(np.median([r[1] for r in rows]))
+    return {"surrogate_ms": t_sur * 1e3, "batched_cv_ms": t_cv * 1e3, "speedup": t_cv / t_sur,
+            "cv_score_ratio_max": float(max(r[2] for r in rows)), "fallbacks": int(sum(r[3] for r in rows)),
+            "datasets": n_datasets, "jobs_per_cv": len(S.H_GRID) * S.N_FOLDS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +197,7 @@ def main():
                      "traffic": None, "alg_bytes_per_node": 12},
         "evals_top3": [float(v) for v in bufs.evals[:3]],
     }
+    out["hselect"] = hselect_timing(h, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         G_host = bufs.G.cpu().numpy().astype(np.float64)
