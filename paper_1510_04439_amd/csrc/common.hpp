@@ -25,6 +25,12 @@ struct fpca_context {
   // the first).
   void *ws3 = nullptr;
   size_t ws3_size = 0;
+  // Captured batched-CV graph: valid for the shape and scratch layout in cv_key.
+  std::vector<double> cv_key;
+  int cv_key_seen = 0;  // eager runs with this key so far
+  hipGraphExec_t cv_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
   // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
   int *d_flags = nullptr;
   int *h_flags = nullptr;  // pinned mirror

@@ -177,6 +177,10 @@ int fpca_destroy(fpca_handle ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ws2) (void)hipFree(ctx->ws2);
   if (ctx->ws3) (void)hipFree(ctx->ws3);
+  if (ctx->cv_exec) (void)hipGraphExecDestroy(ctx->cv_exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+  if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   delete ctx;

@@ -61,29 +61,101 @@ int cv_impl(fpca_context *ctx, const fpca_grid *grid, int dtype, int n_folds, co
   const GridDims gd = make_dims(grid);
   const int64_t P = gd.P, PP = P * P;
   const int njobs = n_h * n_folds;
-  const size_t need = 3 * carve_bytes(PP, sizeof(T)) + carve_bytes(size_t(njobs) * SCORE_BLOCKS, 8) +
-                      carve_bytes(njobs, 8);
+  const int64_t nin = (int64_t(n_folds) + 1) * PP;
+  const size_t need = 3 * carve_bytes(nin, sizeof(T)) + 3 * carve_bytes(PP, sizeof(T)) +
+                      carve_bytes(size_t(njobs) * SCORE_BLOCKS, 8) + carve_bytes(njobs, 8);
   if (int rc = ws3_reserve(ctx, need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws3), 0, ctx->ws3_size};
+  // inputs are staged into the handle's buffers, so a captured graph depends
+  // only on the shape and not on the caller's pointers
+  T *Cs = cv.take<T>(nin);
+  T *Gs = cv.take<T>(nin);
+  T *Qs = cv.take<T>(nin);
   T *W = cv.take<T>(PP);
   T *S = cv.take<T>(PP);
   T *Gh = cv.take<T>(PP);
   double *part = cv.take<double>(size_t(njobs) * SCORE_BLOCKS);
   double *sc = cv.take<double>(njobs);
+  FPCA_HIP(hipMemcpyAsync(Cs, C, sizeof(T) * nin, hipMemcpyDeviceToDevice, ctx->stream));
+  FPCA_HIP(hipMemcpyAsync(Gs, G, sizeof(T) * nin, hipMemcpyDeviceToDevice, ctx->stream));
+  FPCA_HIP(hipMemcpyAsync(Qs, Q, sizeof(T) * nin, hipMemcpyDeviceToDevice, ctx->stream));
   int64_t blocks = (PP + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  for (int f = 0; f < n_folds; ++f) {
-    const int64_t o = (int64_t(f) + 1) * PP;
-    hipLaunchKernelGGL(k_fold_diff<T>, dim3(unsigned(blocks)), dim3(256), 0, ctx->stream, PP, C, C + o, G, G + o, W, S);
-    FPCA_LAUNCH_CHECK("fold_diff");
-    for (int hi = 0; hi < n_h; ++hi) {
-      if (int rc = smooth_cov_internal(ctx, grid, dtype, W, 0.0, S, nullptr, bw + int64_t(hi) * grid->d, Gh, nullptr))
-        return rc;
-      const int job = hi * n_folds + f;
-      hipLaunchKernelGGL(k_cv_score<T>, dim3(SCORE_BLOCKS), dim3(256), 0, ctx->stream, PP, Q + o, G + o, C + o, Gh,
-                         part + int64_t(job) * SCORE_BLOCKS);
-      FPCA_LAUNCH_CHECK("cv_score");
+
+  auto queue_jobs = [&]() -> int {
+    for (int f = 0; f < n_folds; ++f) {
+      const int64_t o = (int64_t(f) + 1) * PP;
+      hipLaunchKernelGGL(k_fold_diff<T>, dim3(unsigned(blocks)), dim3(256), 0, ctx->stream, PP, Cs, Cs + o, Gs,
+                         Gs + o, W, S);
+      FPCA_LAUNCH_CHECK("fold_diff");
+      for (int hi = 0; hi < n_h; ++hi) {
+        if (int rc = smooth_cov_internal(ctx, grid, dtype, W, 0.0, S, nullptr, bw + int64_t(hi) * grid->d, Gh,
+                                         nullptr))
+          return rc;
+        const int job = hi * n_folds + f;
+        hipLaunchKernelGGL(k_cv_score<T>, dim3(SCORE_BLOCKS), dim3(256), 0, ctx->stream, PP, Qs + o, Gs + o, Cs + o,
+                           Gh, part + int64_t(job) * SCORE_BLOCKS);
+        FPCA_LAUNCH_CHECK("cv_score");
+      }
     }
+    return FPCA_OK;
+  };
+  // The job sequence is captured into a graph on its second call with the
+  // same shape and scratch layout (the first, eager call sizes every scratch
+  // buffer, so capture performs no allocation) and replayed afterwards.
+  auto make_key = [&]() {
+    std::vector<double> k = {double(dtype), double(grid->d), double(n_folds), double(n_h),
+                             double(reinterpret_cast<uintptr_t>(grid->mask)),
+                             double(reinterpret_cast<uintptr_t>(ctx->ws)), double(ctx->ws_size),
+                             double(reinterpret_cast<uintptr_t>(ctx->ws3)), double(ctx->ws3_size)};
+    for (int q = 0; q < grid->d; ++q) k.push_back(double(grid->M[q]));
+    for (int i = 0; i < n_h * grid->d; ++i) k.push_back(bw[i]);
+    return k;
+  };
+  const std::vector<double> key = make_key();
+  const bool same = (key == ctx->cv_key);
+  if (same && ctx->cv_exec) {
+    FPCA_HIP(hipEventRecord(ctx->ev_a, ctx->stream));
+    FPCA_HIP(hipStreamWaitEvent(ctx->cap_stream, ctx->ev_a, 0));
+    FPCA_HIP(hipGraphLaunch(ctx->cv_exec, ctx->cap_stream));
+    FPCA_HIP(hipEventRecord(ctx->ev_b, ctx->cap_stream));
+    FPCA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
+  } else if (same && ctx->cv_key_seen >= 1) {
+    if (!ctx->cap_stream) {
+      FPCA_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      FPCA_HIP(hipEventCreateWithFlags(&ctx->ev_a, hipEventDisableTiming));
+      FPCA_HIP(hipEventCreateWithFlags(&ctx->ev_b, hipEventDisableTiming));
+    }
+    FPCA_HIP(hipEventRecord(ctx->ev_a, ctx->stream));
+    FPCA_HIP(hipStreamWaitEvent(ctx->cap_stream, ctx->ev_a, 0));
+    hipStream_t user = ctx->stream;
+    FPCA_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    ctx->stream = ctx->cap_stream;
+    const int rc = queue_jobs();
+    ctx->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc != FPCA_OK || ec != hipSuccess || make_key() != key) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      ctx->cv_key.clear();
+      ctx->cv_key_seen = 0;
+      if (rc != FPCA_OK) return rc;
+      return set_error(FPCA_ERR_DEVICE, "batched CV graph capture failed");
+    }
+    if (ctx->cv_exec) (void)hipGraphExecDestroy(ctx->cv_exec);
+    ctx->cv_exec = nullptr;
+    FPCA_HIP(hipGraphInstantiate(&ctx->cv_exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    FPCA_HIP(hipGraphLaunch(ctx->cv_exec, ctx->cap_stream));
+    FPCA_HIP(hipEventRecord(ctx->ev_b, ctx->cap_stream));
+    FPCA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
+  } else {
+    if (int rc = queue_jobs()) return rc;
+    if (ctx->cv_exec) (void)hipGraphExecDestroy(ctx->cv_exec);
+    ctx->cv_exec = nullptr;
+    ctx->cv_key = make_key();  // after the run: the scratch it sized
+    ctx->cv_key_seen = 1;
   }
   hipLaunchKernelGGL(k_cv_finish, dim3((njobs + 63) / 64), dim3(64), 0, ctx->stream, njobs, part, sc);
   FPCA_LAUNCH_CHECK("cv_finish");

@@ -129,6 +129,18 @@ __global__ void k_offdiag_fill(T *A, int64_t P, T v) {
 
 inline unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
 
+// taps[j][m + R] = (1 - u^2) u^j, u = m / (h (M-1)), 0 for |u| >= 1 (j = 0, 1, 2).
+template <typename T>
+__global__ void k_taps(double h, int M, int R, T *taps) {
+  const int W = 2 * R + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * W) return;
+  const int j = e / W, m = e % W - R;
+  const double u = double(m) / (h * double(M - 1));
+  const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
+  taps[e] = T(K * (j == 0 ? 1.0 : (j == 1 ? u : u * u)));
+}
+
 // 1-D taps (1 - u^2) u^j at offsets m = -R..R, u = m / (h (M-1)), zero for |u| >= 1.
 int tap_radius(double h, int M) { return int(std::floor(h * double(M - 1))); }
 
@@ -147,20 +159,12 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
     if (R[k] > 4096) return set_error(FPCA_ERR_UNSUPPORTED, "bandwidth spans too many grid steps");
     tap_count += 3 * size_t(2 * R[k] + 1);
   }
-  std::vector<T> taps_h(tap_count);
   std::vector<size_t> tap_off(D);
   {
     size_t o = 0;
     for (int k = 0; k < D; ++k) {
       tap_off[k] = o;
-      const int W = 2 * R[k] + 1;
-      for (int j = 0; j < 3; ++j)
-        for (int m = -R[k]; m <= R[k]; ++m) {
-          const double u = double(m) / (h[k] * double(dims[k] - 1));
-          const double K = std::fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
-          taps_h[o + j * W + (m + R[k])] = T(K * std::pow(u, j));
-        }
-      o += 3 * W;
+      o += 3 * size_t(2 * R[k] + 1);
     }
   }
   // Plan the passes: coordinates from the last (contiguous) to the first.
@@ -191,7 +195,14 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
   T *bufA = cv.take<T>(maxA * size_t(total));
   T *bufB = cv.take<T>(maxB * size_t(total));
   T *taps = cv.take<T>(tap_count);
-  FPCA_HIP(hipMemcpyAsync(taps, taps_h.data(), tap_count * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  // tap tables are computed on the device (no host buffer in the stream: the
+  // sequence can be captured into a graph)
+  for (int k = 0; k < D; ++k) {
+    const int W = 2 * R[k] + 1;
+    hipLaunchKernelGGL(k_taps<T>, dim3(unsigned((3 * W + 255) / 256)), dim3(256), 0, ctx->stream, h[k], dims[k],
+                       R[k], taps + tap_off[k]);
+    FPCA_LAUNCH_CHECK("taps");
+  }
 
   std::vector<const T *> cur = {w, g};
   for (int s = 0; s < D; ++s) {

@@ -458,8 +458,12 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C
   const size_t lds_t = size_t((analytic ? 1 : 2) + (analytic ? 2 : 5)) * size_t(M1) * (M2 + 1) * sizeof(float);
 #define STAGE_T(A, RR)                                                                                        \
   do {                                                                                                        \
-    FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<A, RR>),                          \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));                    \
+    static int lds_set = 0; /* the attribute is set once per size (not inside a captured stream) */          \
+    if (lds_set < int(lds_t)) {                                                                               \
+      FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<A, RR>),                        \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));                  \
+      lds_set = int(lds_t);                                                                                   \
+    }                                                                                                         \
     hipLaunchKernelGGL((k_stage_t<A, RR>), dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, \
                        tp, U);                                                                                \
   } while (0)
