@@ -90,9 +90,9 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
   const int64_t c0 = int64_t(blockIdx.x) * 64;
   const int64_t k0 = int64_t(blockIdx.y) * kchunk;
   const int64_t k1 = min(P, k0 + kchunk);
-  float4_t acc[RB];
+  float4_t acc[2][RB];  // two sets alternate over K steps: independent MFMA chains
 #pragma unroll
-  for (int b = 0; b < RB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < RB; ++b) acc[0][b] = acc[1][b] = float4_t{0.f, 0.f, 0.f, 0.f};
   const int ar = tid >> 4, ac = (tid & 15) * 4;  // rows ar and ar+16, columns ac..ac+3
   float ra[2][4], rx[2][4];
   auto load = [&](int64_t kb) {
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
 #pragma unroll
       for (int mb = 0; mb < RB; ++mb) {
         const float a = Xs[buf][krow][mb * 16 + (lane & 15)];
-        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[mb], 0, 0, 0);
+        acc[(kk >> 2) & 1][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[(kk >> 2) & 1][mb], 0, 0, 0);
       }
     }
     if (more) store(buf ^ 1);
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
 #pragma unroll
     for (int mb = 0; mb < RB; ++mb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[mb * 16 + 4 * (lane >> 4) + v] = acc[mb][v];
+      for (int v = 0; v < 4; ++v) dst[mb * 16 + 4 * (lane >> 4) + v] = acc[0][mb][v] + acc[1][mb][v];
   }
 }
 

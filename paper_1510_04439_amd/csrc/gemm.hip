@@ -263,14 +263,20 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const unsigned short *__res
       bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bh][c][kq]));
       blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bl][c][kq]));
     }
+    // the three products of a block are 16 MFMAs apart (independent
+    // accumulators in between), so no MFMA waits on its predecessor
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
-      }
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
