@@ -96,6 +96,37 @@ def hselect_timing(h, torch, n_datasets: int = 5):
             "datasets": n_datasets, "jobs_per_cv": len(S.H_GRID) * S.N_FOLDS}
 
 
+def cv_d3_timing(h, torch, F):
+    """Batched CV on the d=3 disk x time workload: n=800 curves, 16^3 grid with
+    the domain mask, covariance on 16^6 = 16.8M nodes (7x7 per-node systems),
+    16 bandwidths x 5 leave-curves-out folds (80 smoother jobs)."""
+    from fpca_synth import make_c4
+    log("batched CV, d=3 (16 bandwidths x 5 folds on 16^6 nodes)")
+    ds = make_c4()
+    P = int(np.prod(ds.M_cov))
+    dev = "cuda:0"
+    off = torch.from_numpy(ds.offsets).to(dev)
+    t = torch.from_numpy(ds.t).to(dev)
+    y = torch.from_numpy(ds.y).to(dev)
+    folds = torch.from_numpy(ds.folds).to(dev)
+    mask = torch.from_numpy(ds.mask).to(dev)
+    grid = F.Grid(ds.M_cov, mask)
+    C, G, Q = (torch.empty(ds.n_folds + 1, P, P, dtype=torch.float32, device=dev) for _ in range(3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fpca_bin(h, grid, F.FPCA_BIN_COV, F.FPCA_IRREGULAR, F.FPCA_F32, F.FPCA_PREC_F32, ds.n, off, t, y, folds,
+               ds.n_folds, C, G, Q)
+    torch.cuda.synchronize()
+    t_bin = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sc = F.fpca_cv_batched(h, grid, F.FPCA_F32, ds.n_folds, C, G, Q, ds.h_grid)
+    t_cv = time.perf_counter() - t0
+    tot = sc.sum(1)
+    return {"bin_ms": t_bin * 1e3, "cv_ms": t_cv * 1e3, "jobs": int(sc.size),
+            "nodes_per_job": P * P, "h_best": float(ds.h_grid[int(np.argmin(tot))]),
+            "node_solves_per_s": sc.size * P * P / t_cv}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--gram-prec", choices=["bf16x3", "f32"], default="bf16x3",
                     help="precision of the binning Gram product (bf16 hi/lo x3 with FP32 accumulation, or FP32)")
@@ -198,6 +230,8 @@ def main():
         "evals_top3": [float(v) for v in bufs.evals[:3]],
     }
     out["hselect"] = hselect_timing(h, torch)
+    if not args.no_cv_d3:
+        out["cv_d3"] = cv_d3_timing(h, torch, F)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         G_host = bufs.G.cpu().numpy().astype(np.float64)
