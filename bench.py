@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
     ap.add_argument("--gram-prec", choices=["bf16x3", "f32"], default="bf16x3",
                     help="precision of the binning Gram product (bf16 hi/lo x3 with FP32 accumulation, or FP32)")
     args = ap.parse_args()
@@ -144,6 +146,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
     import paper_1510_04439_amd as F
     from paper_1510_04439_amd import pipeline as PL
     from fpca_synth import make_c3

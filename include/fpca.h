@@ -145,6 +145,9 @@ int fpca_bin(fpca_handle handle, const fpca_grid *grid, int kind, int design, in
  *   mu: P outputs of `dtype`; status: optional P int8 (FPCA_STATUS_*).
  * Status rule: EMPTY if S0 == 0; FALLBACK if a diagonal entry is 0 or the
  * Jacobi-scaled Cholesky factorization has a pivot below 1e-10; else OK.
+ * Precision: the moments are accumulated and the system solved in FP64 for
+ * either storage dtype, so windows that are exactly degenerate (sparse bins,
+ * data on one side of the node) are recognized as such.
  */
 int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const void *weights,
                      const void *sums, int kernel, const double *bandwidth, void *mu,
@@ -165,6 +168,10 @@ int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const
  *      return the raw second-moment surface b0 (symmetrized) instead.
  *   bandwidth: host array of d bandwidths; the s- and t-coordinates share them.
  *   gamma: P x P output of `dtype`; status: optional P x P int8.
+ * Precision: with C given, FP64 moments and solve (as for the mean). With
+ * C = NULL and dtype F32 on a d = 2 grid, the weight moments are exact FP64
+ * closed forms and the response moments FP32 sums; only b0 at p <= q is
+ * evaluated and mirrored, the two fits being equal in exact arithmetic.
  */
 int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const void *C,
                     double c_uniform, const void *G, const void *mu, int kernel,

@@ -7,7 +7,8 @@
 // factor over the coordinates because the kernel is a product: along each
 // coordinate in turn, every partial moment array is correlated with the 1-D
 // taps (1-u^2)u^j, j = 0..(remaining degree). This file holds the general
-// pass-per-coordinate engine for D <= 6 and the per-node FP64 solve.
+// pass-per-coordinate engine for D <= 6 (partial moments in FP64 for either
+// storage type) and the per-node FP64 solve.
 #include <cmath>
 #include <vector>
 
@@ -16,8 +17,8 @@
 
 namespace fpca {
 
-int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, double c0, const float *G,
-                        const double *bw, const float *mu, float *gamma, int8_t *status);
+int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, double c0, const float *G, const double *bw,
+                        const float *mu, float *gamma, int8_t *status);
 bool smooth_cov_fused_d2_supported(const fpca_grid *grid, const double *bw);
 
 namespace {
@@ -35,30 +36,34 @@ struct MomArray {
   }
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int Mk, const T *__restrict__ src,
-                                               int nj, T *__restrict__ o0, T *__restrict__ o1, T *__restrict__ o2,
-                                               const T *__restrict__ taps, int R) {
+// One coordinate pass: o_j[e] = sum_m taps_j[m] src[e + m stride]. The source
+// is the FP32 or FP64 input on the first pass and an FP64 partial moment after
+// it; the partial moments and taps are FP64 so that the normal equations of
+// nearly degenerate windows (sparse bins, data on one side of the node) keep
+// their singular structure to FP64 rounding.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int Mk, const TS *__restrict__ src,
+                                               int nj, double *__restrict__ o0, double *__restrict__ o1,
+                                               double *__restrict__ o2, const double *__restrict__ taps, int R) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int xk = int((e / stride) % Mk);
   const int lo = -min(R, xk), hi = min(R, Mk - 1 - xk);
   const int W = 2 * R + 1;
-  T a0 = T(0), a1 = T(0), a2 = T(0);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int m = lo; m <= hi; ++m) {
-    const T v = src[e + int64_t(m) * stride];
-    a0 += taps[m + R] * v;
-    if (nj > 1) a1 += taps[W + m + R] * v;
-    if (nj > 2) a2 += taps[2 * W + m + R] * v;
+    const double v = double(src[e + int64_t(m) * stride]);
+    a0 = fma(taps[m + R], v, a0);
+    if (nj > 1) a1 = fma(taps[W + m + R], v, a1);
+    if (nj > 2) a2 = fma(taps[2 * W + m + R], v, a2);
   }
   o0[e] = a0;
   if (nj > 1) o1[e] = a1;
   if (nj > 2) o2[e] = a2;
 }
 
-template <typename T>
 struct MomPtrs {
-  const T *p[MAXMOM];
+  const double *p[MAXMOM];
 };
 
 }  // namespace
@@ -66,14 +71,14 @@ struct MomPtrs {
 namespace {
 
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_wls(int64_t total, MomPtrs<T> mp, T *__restrict__ out,
+__global__ __launch_bounds__(256) void k_wls(int64_t total, MomPtrs mp, T *__restrict__ out,
                                               int8_t *__restrict__ status) {
   constexpr int NM = 1 + D + D * (D + 1) / 2 + 1 + D;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= total) return;
   double m[NM];
 #pragma unroll
-  for (int i = 0; i < NM; ++i) m[i] = double(mp.p[i][e]);
+  for (int i = 0; i < NM; ++i) m[i] = mp.p[i][e];
   int8_t st;
   const double b0 = wls_b0<D>(m, &st);
   out[e] = T(b0);
@@ -130,15 +135,14 @@ __global__ void k_offdiag_fill(T *A, int64_t P, T v) {
 inline unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
 
 // taps[j][m + R] = (1 - u^2) u^j, u = m / (h (M-1)), 0 for |u| >= 1 (j = 0, 1, 2).
-template <typename T>
-__global__ void k_taps(double h, int M, int R, T *taps) {
+__global__ void k_taps(double h, int M, int R, double *taps) {
   const int W = 2 * R + 1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 3 * W) return;
   const int j = e / W, m = e % W - R;
   const double u = double(m) / (h * double(M - 1));
   const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
-  taps[e] = T(K * (j == 0 ? 1.0 : (j == 1 ? u : u * u)));
+  taps[e] = K * (j == 0 ? 1.0 : (j == 1 ? u : u * u));
 }
 
 // 1-D taps (1 - u^2) u^j at offsets m = -R..R, u = m / (h (M-1)), zero for |u| >= 1.
@@ -187,49 +191,53 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
     else
       maxB = std::max(maxB, lists[s + 1].size());
   }
-  const size_t bytesA = carve_bytes(maxA * size_t(total), sizeof(T));
-  const size_t bytesB = carve_bytes(maxB * size_t(total), sizeof(T));
-  const size_t bytesT = carve_bytes(tap_count, sizeof(T));
+  const size_t bytesA = carve_bytes(maxA * size_t(total), sizeof(double));
+  const size_t bytesB = carve_bytes(maxB * size_t(total), sizeof(double));
+  const size_t bytesT = carve_bytes(tap_count, sizeof(double));
   if (int rc = ws_reserve(ctx, bytesA + bytesB + bytesT)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
-  T *bufA = cv.take<T>(maxA * size_t(total));
-  T *bufB = cv.take<T>(maxB * size_t(total));
-  T *taps = cv.take<T>(tap_count);
+  double *bufA = cv.take<double>(maxA * size_t(total));
+  double *bufB = cv.take<double>(maxB * size_t(total));
+  double *taps = cv.take<double>(tap_count);
   // tap tables are computed on the device (no host buffer in the stream: the
   // sequence can be captured into a graph)
   for (int k = 0; k < D; ++k) {
     const int W = 2 * R[k] + 1;
-    hipLaunchKernelGGL(k_taps<T>, dim3(unsigned((3 * W + 255) / 256)), dim3(256), 0, ctx->stream, h[k], dims[k],
+    hipLaunchKernelGGL(k_taps, dim3(unsigned((3 * W + 255) / 256)), dim3(256), 0, ctx->stream, h[k], dims[k],
                        R[k], taps + tap_off[k]);
     FPCA_LAUNCH_CHECK("taps");
   }
 
-  std::vector<const T *> cur = {w, g};
+  std::vector<const double *> cur;
   for (int s = 0; s < D; ++s) {
     const int k = D - 1 - s;
-    T *dst = (s % 2 == 0) ? bufA : bufB;
-    std::vector<const T *> next;
+    double *dst = (s % 2 == 0) ? bufA : bufB;
+    std::vector<const double *> next;
     size_t o = 0;
     for (size_t a = 0; a < lists[s].size(); ++a) {
       const MomArray &m = lists[s][a];
       const int nj = (m.fam == 0 ? 2 : 1) - m.deg() + 1;
-      T *outs[3] = {nullptr, nullptr, nullptr};
+      double *outs[3] = {nullptr, nullptr, nullptr};
       for (int j = 0; j < nj; ++j) {
         outs[j] = dst + (o + j) * size_t(total);
         next.push_back(outs[j]);
       }
-      hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k], dims[k],
-                         cur[a], nj, outs[0], outs[1] ? outs[1] : outs[0], outs[2] ? outs[2] : outs[0],
-                         taps + tap_off[k], R[k]);
+      double *o1 = outs[1] ? outs[1] : outs[0], *o2 = outs[2] ? outs[2] : outs[0];
+      if (s == 0)  // the inputs, in their storage type
+        hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k], dims[k],
+                           a == 0 ? w : g, nj, outs[0], o1, o2, taps + tap_off[k], R[k]);
+      else
+        hipLaunchKernelGGL(k_pass<double>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k],
+                           dims[k], cur[a], nj, outs[0], o1, o2, taps + tap_off[k], R[k]);
       FPCA_LAUNCH_CHECK("moment pass");
       o += nj;
     }
     cur.swap(next);
   }
   // Gather the final arrays in moment order.
-  MomPtrs<T> mp{};
+  MomPtrs mp{};
   const std::vector<MomArray> &fin = lists[D];
-  auto find = [&](int fam, const int *e) -> const T * {
+  auto find = [&](int fam, const int *e) -> const double * {
     for (size_t i = 0; i < fin.size(); ++i) {
       if (fin[i].fam != fam) continue;
       bool eq = true;
@@ -304,8 +312,8 @@ int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double
   const int64_t P = gd.P;
   const int d = grid->d;
   if constexpr (sizeof(T) == 4) {
-    if (d == 2 && smooth_cov_fused_d2_supported(grid, bw))
-      return smooth_cov_fused_d2(ctx, grid, C, c_uniform, G, bw, mu, gamma, status);
+    if (!C && smooth_cov_fused_d2_supported(grid, bw))
+      return smooth_cov_fused_d2(ctx, grid, c_uniform, G, bw, mu, gamma, status);
   }
   int dims[MAXD];
   double h[MAXD];

@@ -1,9 +1,9 @@
-// Fused covariance smoother for d = 2 (eq. 2.4 on the 4-dimensional grid of
-// (s1, s2, t1, t2)), in two kernels:
+// Fused covariance smoother for d = 2 on a complete common grid (eq. 2.4 on
+// the 4-dimensional grid of (s1, s2, t1, t2)), in two kernels:
 //
-//  stage T: one workgroup per s-row of C and G (a whole t-plane, held in LDS):
-//           the t2 and t1 passes produce the partial moments in t,
-//           G: (t-exponents) 00, 10, 01;  C: 00, 10, 01, 20, 11, 02.
+//  stage T: one workgroup per s-row of G (a whole t-plane, held in LDS): the
+//           t2 and t1 passes produce the partial moments G00, G10, G01
+//           (t-exponents).
 //  stage S: a workgroup owns 8 consecutive t columns, one wavefront per
 //           column, lane = s2. It streams the s1 rows of the partial moments
 //           (staged through LDS for coalescing), keeps a register window of
@@ -12,9 +12,11 @@
 //           computed (the surface is symmetric); each is written at (p,q)
 //           and (q,p) with mu(p)mu(q) subtracted and the domain mask applied.
 //
-// When C is the complete common-grid pair weight c0 (1 - delta_pq), the 15
-// weight moments are exact products of 1-D tap sums minus the diagonal part,
-// evaluated in FP64 from small tables; only G is convolved.
+// The pair weights are c0 (1 - delta_pq), so the 15 weight moments are exact
+// products of 1-D tap sums minus the diagonal part, evaluated in FP64 from
+// small tables; only G is convolved (FP32). These systems are those of a
+// complete design, well conditioned at every node; general pair weights go
+// through the FP64 engine, whose windows may be nearly degenerate.
 #include <cmath>
 
 #include "common.hpp"
@@ -90,63 +92,47 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
 }
 
 // ---------------------------------------------------------------- stage T
-// U layout: NU arrays of P x P (row s, column t). Array order:
-//   0 G00, 1 G10, 2 G01, [3 C00, 4 C10, 5 C01, 6 C20, 7 C11, 8 C02]
-// (exponents of u in (t1, t2)).
-template <bool ANALYTIC, int R>
-__global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, const float *__restrict__ C,
-                                                  const float *__restrict__ G, Taps tp, float *__restrict__ U) {
-  constexpr int NA = ANALYTIC ? 2 : 5;  // t2-pass arrays: GK GU [CK CU CUU]
-  constexpr int NB = 4;                 // consecutive outputs per thread
+// U layout: 3 arrays of P x P (row s, column t): G00, G10, G01 (exponents of
+// u in (t1, t2)).
+template <int R>
+__global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, const float *__restrict__ G, Taps tp,
+                                                  float *__restrict__ U) {
+  constexpr int NB = 4;  // consecutive outputs per thread
   constexpr int WIN = NB + 2 * R;
   extern __shared__ float lds[];
   const int LD = M2 + 1;  // padded t-plane row: both passes are bank-conflict free
   const int plane = M1 * LD;
   float *rowG = lds;
-  float *rowC = lds + plane;
-  float *A = lds + (ANALYTIC ? 1 : 2) * plane;  // NA planes
+  float *A = lds + plane;  // t2-pass planes GK, GU
   const int64_t s = blockIdx.x;
   const int tid = threadIdx.x;
   for (int64_t e = tid; e < P; e += blockDim.x) {
     const int t1 = int(e / M2), t2 = int(e % M2);
     rowG[t1 * LD + t2] = G[s * P + e];
-    if (!ANALYTIC) rowC[t1 * LD + t2] = C[s * P + e];
   }
   __syncthreads();
   // t2 pass: thread -> (strip of NB outputs along t2, line t1), t1 fastest
   const int nst2 = (M2 + NB - 1) / NB;
   for (int sidx = tid; sidx < nst2 * M1; sidx += blockDim.x) {
     const int t1 = sidx % M1, t20 = (sidx / M1) * NB;
-    float wg[WIN], wc[WIN];
+    float wg[WIN];
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {
       const int t2 = t20 - R + i;
-      const bool in = t2 >= 0 && t2 < M2;
-      wg[i] = in ? rowG[t1 * LD + t2] : 0.f;
-      if (!ANALYTIC) wc[i] = in ? rowC[t1 * LD + t2] : 0.f;
+      wg[i] = (t2 >= 0 && t2 < M2) ? rowG[t1 * LD + t2] : 0.f;
     }
 #pragma unroll
     for (int o = 0; o < NB; ++o) {
-      float gk = 0.f, gu = 0.f, ck = 0.f, cu = 0.f, cuu = 0.f;
+      float gk = 0.f, gu = 0.f;
 #pragma unroll
       for (int m = 0; m <= 2 * R; ++m) {
         gk = fmaf(tp.k[0][m], wg[o + m], gk);
         gu = fmaf(tp.k[1][m], wg[o + m], gu);
-        if (!ANALYTIC) {
-          ck = fmaf(tp.k[0][m], wc[o + m], ck);
-          cu = fmaf(tp.k[1][m], wc[o + m], cu);
-          cuu = fmaf(tp.k[2][m], wc[o + m], cuu);
-        }
       }
       if (t20 + o < M2) {
         const int e = t1 * LD + t20 + o;
-        A[0 * plane + e] = gk;
-        A[1 * plane + e] = gu;
-        if (!ANALYTIC) {
-          A[2 * plane + e] = ck;
-          A[3 * plane + e] = cu;
-          A[4 * plane + e] = cuu;
-        }
+        A[e] = gk;
+        A[plane + e] = gu;
       }
     }
   }
@@ -156,13 +142,13 @@ __global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, cons
   const int nst1 = (M1 + NB - 1) / NB;
   for (int sidx = tid; sidx < nst1 * M2; sidx += blockDim.x) {
     const int t2 = sidx % M2, t10 = (sidx / M2) * NB;
-    float out[ANALYTIC ? 3 : 9][NB];
+    float out[3][NB];
 #pragma unroll
-    for (int q = 0; q < (ANALYTIC ? 3 : 9); ++q)
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int o = 0; o < NB; ++o) out[q][o] = 0.f;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
+    for (int a = 0; a < 2; ++a) {
       float w[WIN];
 #pragma unroll
       for (int i = 0; i < WIN; ++i) {
@@ -174,22 +160,12 @@ __global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, cons
 #pragma unroll
         for (int m = 0; m <= 2 * R; ++m) {
           const float v = w[o + m];
-          // t2-pass array a -> outputs (t1 exponent): GK->G00,G10; GU->G01;
-          // CK->C00,C10,C20; CU->C01,C11; CUU->C02
+          // GK -> G00, G10; GU -> G01
           if (a == 0) {
             out[0][o] = fmaf(tp.k[0][m], v, out[0][o]);
             out[1][o] = fmaf(tp.k[1][m], v, out[1][o]);
-          } else if (a == 1) {
-            out[2][o] = fmaf(tp.k[0][m], v, out[2][o]);
-          } else if (a == 2) {
-            out[3][o] = fmaf(tp.k[0][m], v, out[3][o]);
-            out[4][o] = fmaf(tp.k[1][m], v, out[4][o]);
-            out[6][o] = fmaf(tp.k[2][m], v, out[6][o]);
-          } else if (a == 3) {
-            out[5][o] = fmaf(tp.k[0][m], v, out[5][o]);
-            out[7][o] = fmaf(tp.k[1][m], v, out[7][o]);
           } else {
-            out[8][o] = fmaf(tp.k[0][m], v, out[8][o]);
+            out[2][o] = fmaf(tp.k[0][m], v, out[2][o]);
           }
         }
     }
@@ -198,7 +174,7 @@ __global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, cons
       if (t10 + o >= M1) continue;
       float *u = U + s * P + int64_t(t10 + o) * M2 + t2;
 #pragma unroll
-      for (int q = 0; q < (ANALYTIC ? 3 : 9); ++q) u[q * PP] = out[q][o];
+      for (int q = 0; q < 3; ++q) u[q * PP] = out[q][o];
     }
   }
 }
@@ -240,12 +216,12 @@ __device__ inline float win_conv(const float *win, const Taps &tp) {
   return a;
 }
 
-template <bool ANALYTIC, int R>
+template <int R>
 __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, const float *__restrict__ U, Taps tp,
                                                   const float *__restrict__ mu, const uint8_t *__restrict__ mask,
                                                   double c0, TabPtrs tab, int nchunks, float *__restrict__ gamma,
                                                   int8_t *__restrict__ status) {
-  constexpr int NU = ANALYTIC ? 3 : 9;
+  constexpr int NU = 3;
   constexpr int W = 2 * R + 1;
   __shared__ float stage[2][NU][64][TW + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -274,7 +250,7 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
 
   // static per-lane factors of the analytic weight moments
   double Af[15], Bf[15];
-  if (ANALYTIC) {
+  {
     const int Mm = tab.Mmax;
     const double *W1 = tab.W, *W2 = tab.W + 3 * Mm;
     const double *D2 = tab.Dg + 6 * int64_t(Mm) * Mm;
@@ -343,53 +319,18 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
       m[18] = Tt1;
       m[19] = Tt2;
     }
-    if (ANALYTIC) {
-      const int Mm = tab.Mmax;
-      const double *W1 = tab.W;
-      const double *D1 = tab.Dg;
-      const double w0 = W1[0 * Mm + x], w1 = W1[1 * Mm + x], w2 = W1[2 * Mm + x];
-      const int tt1 = t1;
-      auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
-      const int E1[15][2] = {{0, 0}, {1, 0}, {0, 0}, {0, 1}, {0, 0}, {2, 0}, {1, 0}, {1, 1},
-                             {1, 0}, {0, 0}, {0, 1}, {0, 0}, {0, 2}, {0, 1}, {0, 0}};
+    const int Mm = tab.Mmax;
+    const double *W1 = tab.W;
+    const double *D1 = tab.Dg;
+    const double w0 = W1[0 * Mm + x], w1 = W1[1 * Mm + x], w2 = W1[2 * Mm + x];
+    const int tt1 = t1;
+    auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
+    const int E1[15][2] = {{0, 0}, {1, 0}, {0, 0}, {0, 1}, {0, 0}, {2, 0}, {1, 0}, {1, 1},
+                           {1, 0}, {0, 0}, {0, 1}, {0, 0}, {0, 2}, {0, 1}, {0, 0}};
 #pragma unroll
-      for (int q = 0; q < 15; ++q) {
-        const double wa = E1[q][0] == 0 ? w0 : (E1[q][0] == 1 ? w1 : w2);
-        m[q] = c0 * (wa * Af[q] - d1(E1[q][0], E1[q][1]) * Bf[q]);
-      }
-    } else {
-      const float c00_0 = win_conv<R, 0>(win[3], tp), c00_1 = win_conv<R, 1>(win[3], tp),
-                  c00_2 = win_conv<R, 2>(win[3], tp);
-      const float c10_0 = win_conv<R, 0>(win[4], tp), c10_1 = win_conv<R, 1>(win[4], tp);
-      const float c01_0 = win_conv<R, 0>(win[5], tp), c01_1 = win_conv<R, 1>(win[5], tp);
-      const float c20_0 = win_conv<R, 0>(win[6], tp), c11_0 = win_conv<R, 0>(win[7], tp),
-                  c02_0 = win_conv<R, 0>(win[8], tp);
-      float o3[3], o2[2], o1[1];
-      lane_conv<R, 3>(c00_0, tp, o3);
-      m[0] = o3[0];   // S0
-      m[2] = o3[1];   // S1 s2
-      m[9] = o3[2];   // S2 s2s2
-      lane_conv<R, 2>(c00_1, tp, o2);
-      m[1] = o2[0];   // S1 s1
-      m[6] = o2[1];   // S2 s1s2
-      lane_conv<R, 1>(c00_2, tp, o1);
-      m[5] = o1[0];   // S2 s1s1
-      lane_conv<R, 2>(c10_0, tp, o2);
-      m[3] = o2[0];   // S1 t1
-      m[10] = o2[1];  // S2 s2t1
-      lane_conv<R, 1>(c10_1, tp, o1);
-      m[7] = o1[0];   // S2 s1t1
-      lane_conv<R, 2>(c01_0, tp, o2);
-      m[4] = o2[0];   // S1 t2
-      m[11] = o2[1];  // S2 s2t2
-      lane_conv<R, 1>(c01_1, tp, o1);
-      m[8] = o1[0];   // S2 s1t2
-      lane_conv<R, 1>(c20_0, tp, o1);
-      m[12] = o1[0];  // S2 t1t1
-      lane_conv<R, 1>(c11_0, tp, o1);
-      m[13] = o1[0];  // S2 t1t2
-      lane_conv<R, 1>(c02_0, tp, o1);
-      m[14] = o1[0];  // S2 t2t2
+    for (int q = 0; q < 15; ++q) {
+      const double wa = E1[q][0] == 0 ? w0 : (E1[q][0] == 1 ? w1 : w2);
+      m[q] = c0 * (wa * Af[q] - d1(E1[q][0], E1[q][1]) * Bf[q]);
     }
     if (lane >= M2) continue;
     const int64_t p = int64_t(x) * M2 + lane;
@@ -423,13 +364,12 @@ bool smooth_cov_fused_d2_supported(const fpca_grid *grid, const double *bw) {
   return true;
 }
 
-int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C, double c0, const float *G,
-                        const double *bw, const float *mu, float *gamma, int8_t *status) {
+int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, double c0, const float *G, const double *bw,
+                        const float *mu, float *gamma, int8_t *status) {
   const int M1 = grid->M[0], M2 = grid->M[1];
   const int64_t P = int64_t(M1) * M2;
   const int R = tap_radius(bw[0], M1);
   const double H = bw[0] * double(M1 - 1);
-  const bool analytic = (C == nullptr);
   Taps tp{};
   for (int j = 0; j < 3; ++j)
     for (int m = -R; m <= R; ++m) {
@@ -437,78 +377,61 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, const float *C
       const double K = std::fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
       tp.k[j][m + R] = float(K * (j == 0 ? 1.0 : (j == 1 ? u : u * u)));
     }
-  const int NU = analytic ? 3 : 9;
+  constexpr int NU = 3;
   const int Mmax = M1 > M2 ? M1 : M2;
   const size_t bytesU = carve_bytes(size_t(NU) * P * P, 4);
-  const size_t bytesT = analytic ? carve_bytes(2 * 3 * Mmax, 8) + carve_bytes(2 * 6 * size_t(Mmax) * Mmax, 8) : 0;
+  const size_t bytesT = carve_bytes(2 * 3 * Mmax, 8) + carve_bytes(2 * 6 * size_t(Mmax) * Mmax, 8);
   if (int rc = ws_reserve(ctx, bytesU + bytesT)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
   float *U = cv.take<float>(size_t(NU) * P * P);
   TabPtrs tab{nullptr, nullptr, Mmax};
-  if (analytic) {
-    double *Wt = cv.take<double>(2 * 3 * Mmax);
-    double *Dt = cv.take<double>(2 * 6 * size_t(Mmax) * Mmax);
-    const double H2 = bw[1] * double(M2 - 1);
-    hipLaunchKernelGGL(k_tables, dim3(64, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2),
-                       Mmax, Wt, Dt);
-    FPCA_LAUNCH_CHECK("tables");
-    tab.W = Wt;
-    tab.Dg = Dt;
-  }
-  const size_t lds_t = size_t((analytic ? 1 : 2) + (analytic ? 2 : 5)) * size_t(M1) * (M2 + 1) * sizeof(float);
-#define STAGE_T(A, RR)                                                                                        \
-  do {                                                                                                        \
-    static int lds_set = 0; /* the attribute is set once per size (not inside a captured stream) */          \
-    if (lds_set < int(lds_t)) {                                                                               \
-      FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<A, RR>),                        \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));                  \
-      lds_set = int(lds_t);                                                                                   \
-    }                                                                                                         \
-    hipLaunchKernelGGL((k_stage_t<A, RR>), dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, C, G, \
-                       tp, U);                                                                                \
+  double *Wt = cv.take<double>(2 * 3 * Mmax);
+  double *Dt = cv.take<double>(2 * 6 * size_t(Mmax) * Mmax);
+  const double H2 = bw[1] * double(M2 - 1);
+  hipLaunchKernelGGL(k_tables, dim3(64, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2), Mmax,
+                     Wt, Dt);
+  FPCA_LAUNCH_CHECK("tables");
+  tab.W = Wt;
+  tab.Dg = Dt;
+  const size_t lds_t = 3 * size_t(M1) * (M2 + 1) * sizeof(float);
+#define STAGE_T(RR)                                                                                          \
+  do {                                                                                                       \
+    static int lds_set = 0; /* the attribute is set once per size (not inside a captured stream) */         \
+    if (lds_set < int(lds_t)) {                                                                              \
+      FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_t<RR>),                          \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_t)));                 \
+      lds_set = int(lds_t);                                                                                  \
+    }                                                                                                        \
+    hipLaunchKernelGGL((k_stage_t<RR>), dim3(unsigned(P)), dim3(512), lds_t, ctx->stream, M1, M2, P, G, tp, U); \
   } while (0)
-#define STAGE_T_R(A)               \
-  switch (R) {                     \
-    case 1: STAGE_T(A, 1); break;  \
-    case 2: STAGE_T(A, 2); break;  \
-    case 3: STAGE_T(A, 3); break;  \
-    case 4: STAGE_T(A, 4); break;  \
-    case 5: STAGE_T(A, 5); break;  \
-    case 6: STAGE_T(A, 6); break;  \
-    case 7: STAGE_T(A, 7); break;  \
-    default: STAGE_T(A, 8); break; \
+  switch (R) {
+    case 1: STAGE_T(1); break;
+    case 2: STAGE_T(2); break;
+    case 3: STAGE_T(3); break;
+    case 4: STAGE_T(4); break;
+    case 5: STAGE_T(5); break;
+    case 6: STAGE_T(6); break;
+    case 7: STAGE_T(7); break;
+    default: STAGE_T(8); break;
   }
-  if (analytic) {
-    STAGE_T_R(true)
-  } else {
-    STAGE_T_R(false)
-  }
-#undef STAGE_T_R
 #undef STAGE_T
   FPCA_LAUNCH_CHECK("stage_t");
   const int nchunks = int((P + TW - 1) / TW);
   const int nlines = (nchunks + 3) / 4;
   const int grid_s = ((nlines + 7) / 8) * 32;
-#define STAGE_S(A, RR)                                                                                      \
-  hipLaunchKernelGGL((k_stage_s<A, RR>), dim3(grid_s), dim3(512), 0, ctx->stream, M1, M2, P, U, tp, mu,     \
-                     grid->mask, c0, tab, nchunks, gamma, status)
-#define STAGE_S_R(A)          \
-  switch (R) {                \
-    case 1: STAGE_S(A, 1); break; \
-    case 2: STAGE_S(A, 2); break; \
-    case 3: STAGE_S(A, 3); break; \
-    case 4: STAGE_S(A, 4); break; \
-    case 5: STAGE_S(A, 5); break; \
-    case 6: STAGE_S(A, 6); break; \
-    case 7: STAGE_S(A, 7); break; \
-    default: STAGE_S(A, 8); break; \
+#define STAGE_S(RR)                                                                                          \
+  hipLaunchKernelGGL((k_stage_s<RR>), dim3(grid_s), dim3(512), 0, ctx->stream, M1, M2, P, U, tp, mu, grid->mask, \
+                     c0, tab, nchunks, gamma, status)
+  switch (R) {
+    case 1: STAGE_S(1); break;
+    case 2: STAGE_S(2); break;
+    case 3: STAGE_S(3); break;
+    case 4: STAGE_S(4); break;
+    case 5: STAGE_S(5); break;
+    case 6: STAGE_S(6); break;
+    case 7: STAGE_S(7); break;
+    default: STAGE_S(8); break;
   }
-  if (analytic) {
-    STAGE_S_R(true)
-  } else {
-    STAGE_S_R(false)
-  }
-#undef STAGE_S_R
 #undef STAGE_S
   FPCA_LAUNCH_CHECK("stage_s");
   return FPCA_OK;
