@@ -37,6 +37,31 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c3_64x64_smooth_cov_hbm_traffic.md")
+SMOOTHER_SOURCES = ("paper_1510_04439_amd/csrc/smooth_fused.hip", "paper_1510_04439_amd/csrc/wls.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per fpca_smooth_cov call from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
+    smoother's sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_t = re.search(r"^traffic_bytes_per_call: (\d+)$", text, re.M)
+    m_h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not (m_t and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in SMOOTHER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def cpu_baseline(ds, G_host: np.ndarray, budget_s: float = 15.0):
     """The oracle (never tuned for this) on a bounded sample of the covariance
     nodes: direct-window FP64 local-linear smoother of the raw surface."""
@@ -135,6 +160,7 @@ def main():
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
+    ap.add_argument("--no-hselect", action="store_true", help="skip the surrogate-versus-CV timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
@@ -179,7 +205,7 @@ def main():
                            bufs.mu, bufs.mu_status)
         if ev: ev[1].record(stream)
         F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_COV, dd.design, dd.dtype, gram_prec, dd.n, None, None,
-                   dd.y, None, 0, bufs.extra.setdefault("Cs", torch.empty_like(bufs.G)), bufs.G)
+                   dd.y, None, 0, None, bufs.G)
         if ev: ev[2].record(stream)
         F.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, None, PL.uniform_pair_weight(dd), bufs.G, bufs.mu,
                           F.FPCA_K_EPANECHNIKOV, ds.h_cov, bufs.gamma, bufs.status)
@@ -235,12 +261,12 @@ def main():
                    "gram_prec": args.gram_prec},
         "stages_ms": stage_ms,
         "smooth_cov_pts_per_s": nodes / (sc_ms / 1e3),
-        "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (all its launches)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_node": 12},
+        "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (k_tables, k_stage_t, k_stage_s)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(), "alg_bytes_per_node": 12},
         "evals_top3": [float(v) for v in bufs.evals[:3]],
     }
-    out["hselect"] = hselect_timing(h, torch)
+    out["hselect"] = None if args.no_hselect else hselect_timing(h, torch)
     if not args.no_cv_d3:
         out["cv_d3"] = cv_d3_timing(h, torch, F)
     if not args.no_cpu_baseline:

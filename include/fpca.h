@@ -116,7 +116,9 @@ const char *fpca_last_error(void);
  *   N = offsets[n], both of storage dtype `dtype`.
  * design = FPCA_COMMON_GRID: every curve is observed at all P nodes; offsets and
  *   t must be NULL and y is the n x P row-major matrix of values. The pair
- *   weights are then n/(P(P-1)) off the diagonal and 0 on it.
+ *   weights are then n/(P(P-1)) off the diagonal and 0 on it; for kind = COV
+ *   `weights` may be NULL, and they are then not written (fpca_smooth_cov
+ *   takes them as C = NULL with c_uniform = n/(P(P-1))).
  * dtype: FPCA_F64 or FPCA_F32 storage of t, y and every value output.
  * prec (kind = COV only, the Gram product): FPCA_PREC_F64 (dtype F64),
  *   FPCA_PREC_F32 (FP32 products, FP32 accumulation) or FPCA_PREC_BF16X3

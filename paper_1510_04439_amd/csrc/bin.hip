@@ -89,33 +89,99 @@ __global__ __launch_bounds__(256) void k_bin_mean(GridDims g, int64_t n, const i
   }
 }
 
-// Common grid, mean: column sums of the n x P matrix over a chunk of rows,
-// accumulated in FP64.
+// Common grid, mean: column sums of the n x P matrix (and of its squares) in
+// FP64 over chunks of CS_ROWS rows. A workgroup covers 256 columns (four per
+// lane) of one chunk; wavefront w loads its CS_ROWS/4 rows at once, and the
+// four wavefronts' sums are added in order through LDS. The chunk's sums go
+// to part[chunk][P]; the finish kernel adds the chunks (no atomics).
+constexpr int CS_ROWS = 64;
 template <typename T>
-__global__ __launch_bounds__(256) void k_colsum(int64_t n, int64_t P, int64_t rows_per_chunk,
-                                                 const T *__restrict__ Y, double *acc1, double *acc2) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const int64_t r0 = int64_t(blockIdx.y) * rows_per_chunk;
-  const int64_t r1 = min(n, r0 + rows_per_chunk);
-  double s = 0.0, s2 = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    double v = double(Y[r * P + p]);
-    s += v;
-    s2 += v * v;
+__global__ __launch_bounds__(256) void k_colsum(int64_t n, int64_t P, const T *__restrict__ Y,
+                                                 double *__restrict__ part1, double *__restrict__ part2) {
+  constexpr int RW = CS_ROWS / 4;  // rows per wavefront
+  __shared__ double red[2][4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = int64_t(blockIdx.x) * 256 + 4 * lane;
+  const int64_t r0 = int64_t(blockIdx.y) * CS_ROWS + wave * RW;
+  const bool vec = (P % 4 == 0) && p0 + 3 < P;
+  T v[RW][4];
+#pragma unroll
+  for (int u = 0; u < RW; ++u) {
+    const int64_t r = r0 + u;
+    if (r < n && vec) {
+      if constexpr (sizeof(T) == 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(Y + r * P + p0);
+        v[u][0] = x.x; v[u][1] = x.y; v[u][2] = x.z; v[u][3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[u][e] = Y[r * P + p0 + e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[u][e] = (r < n && p0 + e < P) ? Y[r * P + p0 + e] : T(0);
+    }
   }
-  atomicAdd(&acc1[p], s);
-  if (acc2) atomicAdd(&acc2[p], s2);
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < RW; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double x = double(v[u][e]);
+      s[e] += x;
+      q[e] += x * x;
+    }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    red[0][wave][4 * lane + e] = s[e];
+    red[1][wave][4 * lane + e] = q[e];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  const int64_t p = int64_t(blockIdx.x) * 256 + c;
+  if (p < P) {
+    const int64_t o = int64_t(blockIdx.y) * P + p;
+    part1[o] = (red[0][0][c] + red[0][1][c]) + (red[0][2][c] + red[0][3][c]);
+    if (part2) part2[o] = (red[1][0][c] + red[1][1][c]) + (red[1][2][c] + red[1][3][c]);
+  }
 }
 
+// c = n/P, s = (column sums)/P, s2 = (column sums of squares)/P: eight lanes
+// per column add every eighth chunk (loads in flight together), then the
+// eight sums are combined pairwise.
 template <typename T>
-__global__ void k_colsum_finish(int64_t n, int64_t P, const double *acc1, const double *acc2, T *c, T *s,
-                                T *s2) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  c[p] = T(double(n) / double(P));
-  s[p] = T(acc1[p] / double(P));
-  if (s2) s2[p] = T(acc2[p] / double(P));
+__global__ __launch_bounds__(256) void k_colsum_finish(int64_t n, int64_t P, int nchunks,
+                                                        const double *__restrict__ part1,
+                                                        const double *__restrict__ part2, T *c, T *s, T *s2) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t p = gid >> 3;
+  const int g = int(gid & 7);
+  double a = 0.0, b = 0.0;
+  if (p < P) {
+    for (int k0 = g; k0 < nchunks; k0 += 64) {
+      double va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 8 * u;
+        va[u] = k < nchunks ? part1[int64_t(k) * P + p] : 0.0;
+        vb[u] = (s2 && k < nchunks) ? part2[int64_t(k) * P + p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if (p < P && g == 0) {
+    c[p] = T(double(n) / double(P));
+    s[p] = T(a / double(P));
+    if (s2) s2[p] = T(b / double(P));
+  }
 }
 
 // Row position of each curve when curves are grouped by fold (stable within a
@@ -306,20 +372,19 @@ int bin_impl(fpca_context *ctx, const fpca_grid *grid, int kind, int design, int
       return FPCA_OK;
     }
     // common grid
-    if (int rc = ws_reserve(ctx, 2 * carve_bytes(P, 8))) return rc;
+    const int nchunks = int(n > 0 ? (n + CS_ROWS - 1) / CS_ROWS : 0);
+    const size_t part = carve_bytes(size_t(nchunks > 0 ? nchunks : 1) * P, 8);
+    if (int rc = ws_reserve(ctx, 2 * part)) return rc;
     Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
-    double *acc1 = cv.take<double>(P);
-    double *acc2 = cv.take<double>(P);
-    if (int rc = fill_f64(ctx, acc1, 0.0, P)) return rc;
-    if (int rc = fill_f64(ctx, acc2, 0.0, P)) return rc;
-    const int64_t rows = 64;
-    dim3 grd((unsigned)((P + 255) / 256), (unsigned)(n > 0 ? (n + rows - 1) / rows : 1));
+    double *part1 = cv.take<double>(size_t(nchunks > 0 ? nchunks : 1) * P);
+    double *part2 = cv.take<double>(size_t(nchunks > 0 ? nchunks : 1) * P);
     if (n > 0) {
-      hipLaunchKernelGGL(k_colsum<T>, grd, dim3(256), 0, ctx->stream, n, P, rows, y, acc1, SQ ? acc2 : nullptr);
+      dim3 grd((unsigned)((P + 255) / 256), (unsigned)nchunks);
+      hipLaunchKernelGGL(k_colsum<T>, grd, dim3(256), 0, ctx->stream, n, P, y, part1, SQ ? part2 : nullptr);
       FPCA_LAUNCH_CHECK("colsum");
     }
-    hipLaunchKernelGGL(k_colsum_finish<T>, dim3(unsigned((P + 255) / 256)), dim3(256), 0, ctx->stream, n, P, acc1,
-                       acc2, W, S, SQ);
+    hipLaunchKernelGGL(k_colsum_finish<T>, dim3(unsigned((8 * P + 255) / 256)), dim3(256), 0, ctx->stream, n, P,
+                       nchunks, part1, part2, W, S, SQ);
     FPCA_LAUNCH_CHECK("colsum_finish");
     return FPCA_OK;
   }
@@ -330,13 +395,15 @@ int bin_impl(fpca_context *ctx, const fpca_grid *grid, int kind, int design, int
   if (design == FPCA_COMMON_GRID) {
     const double w = 1.0 / (double(P) * double(P - 1));
     if (int rc = gram<T>(ctx, y, n, P, S, w, true, prec)) return rc;
-    if constexpr (sizeof(T) == 4) {
-      if (int rc = fill_f32(ctx, W, float(double(n) * w), slab)) return rc;
-    } else {
-      if (int rc = fill_f64(ctx, W, double(n) * w, slab)) return rc;
+    if (W) {  // the pair weights n w (1 - delta_pq) are materialized only when asked for
+      if constexpr (sizeof(T) == 4) {
+        if (int rc = fill_f32(ctx, W, float(double(n) * w), slab)) return rc;
+      } else {
+        if (int rc = fill_f64(ctx, W, double(n) * w, slab)) return rc;
+      }
+      hipLaunchKernelGGL(k_set_diag<T>, dim3(grid1(P)), dim3(256), 0, ctx->stream, W, P, T(0));
+      FPCA_LAUNCH_CHECK("set_diag");
     }
-    hipLaunchKernelGGL(k_set_diag<T>, dim3(grid1(P)), dim3(256), 0, ctx->stream, W, P, T(0));
-    FPCA_LAUNCH_CHECK("set_diag");
     if (SQ) {
       if (int rc = ws_reserve(ctx, carve_bytes(size_t(n) * P, sizeof(T)))) return rc;
       T *Y2 = static_cast<T *>(ctx->ws);
@@ -445,7 +512,9 @@ extern "C" int fpca_bin(fpca_handle ctx, const fpca_grid *grid, int kind, int de
     return set_error(FPCA_ERR_INVALID_ARG, "bad design %d", design);
   if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype %d", dtype);
   if (n < 0) return set_error(FPCA_ERR_INVALID_ARG, "n < 0");
-  if (!weights || !sums) return set_error(FPCA_ERR_INVALID_ARG, "weights and sums are required");
+  if (!sums) return set_error(FPCA_ERR_INVALID_ARG, "sums are required");
+  if (!weights && !(kind == FPCA_BIN_COV && design == FPCA_COMMON_GRID))
+    return set_error(FPCA_ERR_INVALID_ARG, "weights are required (optional only for common-grid COV binning)");
   if (!y && n > 0) return set_error(FPCA_ERR_INVALID_ARG, "y is required");
   if (design == FPCA_IRREGULAR) {
     if (!offsets || (!t && n > 0)) return set_error(FPCA_ERR_INVALID_ARG, "irregular design needs offsets and t");

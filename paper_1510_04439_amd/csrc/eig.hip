@@ -5,7 +5,10 @@
 //   test matrix  : counter-based normals (splitmix64 + Box-Muller), P x r
 //   products     : Gamma X on MFMA (FP32) with split K, FP64 reduction
 //   orthonormal  : CholeskyQR2 in FP64 (columns that become numerically
-//                  dependent are dropped: their basis vector is set to 0)
+//                  dependent are dropped: their basis vector is set to 0);
+//                  row kernels on 16-row chunks, a fixed-order sum of the
+//                  partial Gram matrices, a one-wavefront factorization
+
 //   Rayleigh-Ritz: B = Q^T A Q in FP64, eigenpairs by a one-workgroup
 //                  parallel-ordered cyclic Jacobi method in FP64
 //   finalize     : psi = Q U, phi = psi / sqrt(w), sign rule, FVE.
@@ -59,20 +62,6 @@ __global__ void k_default_w(int64_t P, double wv, const uint8_t *mask, double *w
   if (p < P) w[p] = (mask && !mask[p]) ? 0.0 : wv;
 }
 
-
-// sum_{c < n} a[c * stride] with eight independent accumulators, so that the
-// loads are in flight together (fixed summation order: deterministic).
-template <typename T>
-__device__ inline double strided_sum(const T *__restrict__ a, int n, int64_t stride) {
-  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int c = 0;
-  for (; c + 8 <= n; c += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += double(a[int64_t(c + u) * stride]);
-  }
-  for (; c < n; ++c) s[0] += double(a[int64_t(c) * stride]);
-  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-}
 
 // Partial products of Y^T = X^T Gamma over one K chunk (Gamma symmetric):
 // workgroup = (64 nodes, K chunk); 4 wavefronts x 16 nodes; MFMA 16x16x4 FP32
@@ -174,205 +163,297 @@ __global__ void k_panel_f64(int64_t P, int rp, const double *__restrict__ G, con
   Yraw[e] = s;
 }
 
-constexpr int GROWS = 64;  // rows per partial-Gram chunk
+constexpr int ROWS = 16;  // rows per workgroup of the row kernels
+constexpr int RT = 256;   // threads of the row kernels
+constexpr int SG = 16;    // threads per entry in the partial-Gram sum
 
-// Finishes a product and starts the next orthonormalization, 64 rows per
-// workgroup: Y[p, j] = sqrt(w_p) * (sum of the K-split partials, or Yraw for
-// FP64 storage), then the chunk's partial Gram matrix:
+// out = A^T B over the ROWS rows of a workgroup (A, B: [ROWS][RP + 1] in LDS).
+template <int RP>
+__device__ inline void rows_gram(const double *A, const double *B, double *__restrict__ out, int tid) {
+  constexpr int LD = RP + 1;
+  for (int e = tid; e < RP * RP; e += RT) {
+    const int a = e / RP, b = e % RP;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < ROWS; rr += 2) {
+      s0 = fma(A[rr * LD + a], B[rr * LD + b], s0);
+      s1 = fma(A[(rr + 1) * LD + a], B[(rr + 1) * LD + b], s1);
+    }
+    out[e] = s0 + s1;
+  }
+}
+
+// Finishes a product, ROWS rows per workgroup: Y[p, j] = sqrt(w_p) * (sum of
+// the K-split partials in split order, or Yraw for FP64 storage), then the
+// rows' partial Gram matrix:
 //   MODE 1: part = Y_c^T Y_c;  MODE 2: part = Q_c^T Y_c  (Rayleigh-Ritz).
-template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce_gram(int64_t P, int rp, int nsplit, const float *__restrict__ part32,
-                                                      const double *__restrict__ Yraw, const double *__restrict__ w,
-                                                      const double *__restrict__ Q, double *__restrict__ Y,
-                                                      double *__restrict__ gpart) {
-  __shared__ double Ys[GROWS][65];
-  __shared__ double Qs[GROWS][65];
-  const int64_t p0 = int64_t(blockIdx.x) * GROWS;
+// A thread loads sixteen splits of all its entries at once.
+template <int MODE, int RP>
+__global__ __launch_bounds__(RT) void k_rows_gram(int64_t P, int nsplit, const float *__restrict__ part32,
+                                                   const double *__restrict__ Yraw, const double *__restrict__ sw,
+                                                   const double *__restrict__ Q, double *__restrict__ Y,
+                                                   double *__restrict__ gpart) {
+  constexpr int LD = RP + 1;
+  constexpr int NE = ROWS * RP / RT;
+  static_assert(NE * RT == ROWS * RP, "whole entries per thread");
+  __shared__ double Ys[ROWS * LD];
+  __shared__ double Qs[MODE == 2 ? ROWS * LD : 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < GROWS * rp; e += 256) {
-    const int rr = e / rp, j = e % rp;
+  const int64_t p0 = int64_t(blockIdx.x) * ROWS;
+  const int64_t base = p0 * RP, lim = P * RP;
+  double acc[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) acc[u] = 0.0;
+  if (part32) {
+    for (int c = 0; c < nsplit; c += 16) {
+      float v[16][NE];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+          const int64_t o = base + tid + RT * u;
+          v[s][u] = (c + s < nsplit && o < lim) ? part32[int64_t(c + s) * lim + o] : 0.f;
+        }
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int u = 0; u < NE; ++u) acc[u] += double(v[s][u]);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int64_t o = base + tid + RT * u;
+      acc[u] = o < lim ? Yraw[o] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + RT * u;
+    const int rr = e / RP, j = e % RP;
     const int64_t p = p0 + rr;
     double v = 0.0, qv = 0.0;
     if (p < P) {
-      const int64_t o = p * rp + j;
-      if (part32) {
-        v = strided_sum(part32 + o, nsplit, P * rp);
-      } else {
-        v = Yraw[o];
-      }
-      v *= sqrt(w[p]);
-      Y[o] = v;
-      if (MODE == 2) qv = Q[o];
+      v = acc[u] * sw[p];
+      Y[p * RP + j] = v;
+      if (MODE == 2) qv = Q[p * RP + j];
     }
-    Ys[rr][j] = v;
-    if (MODE == 2) Qs[rr][j] = qv;
+    Ys[rr * LD + j] = v;
+    if (MODE == 2) Qs[rr * LD + j] = qv;
   }
   __syncthreads();
-  for (int e = tid; e < rp * rp; e += 256) {
-    const int a = e / rp, b = e % rp;
-    double s = 0.0;
-    for (int rr = 0; rr < GROWS; ++rr) s += (MODE == 2 ? Qs[rr][a] : Ys[rr][a]) * Ys[rr][b];
-    gpart[int64_t(blockIdx.x) * rp * rp + e] = s;
-  }
+  rows_gram<RP>(MODE == 2 ? Qs : Ys, Ys, gpart + int64_t(blockIdx.x) * RP * RP, tid);
 }
 
-// One workgroup: G = sum of the partial Gram matrices; then one wavefront
-// factors G = L L^T right-looking with the rows in registers (column j is
-// broadcast through LDS), dropping numerically dependent columns (pivot <=
-// 1e-12 of the column's squared norm), and inverts L by forward substitution
-// (lane j owns column j of L^{-1}). Rinv = R^{-1} = (L^{-1})^T with the dropped
-// columns zeroed; act[j] = 1 for kept columns.
+// G = sum of the nparts partial RP x RP matrices in a fixed order: thread g
+// of an entry adds partials g, g + SG, g + 2 SG, ... (sixteen loads in
+// flight), then the SG sums are combined pairwise.
 template <int RP>
-__global__ __launch_bounds__(256) void k_chol(int nparts, const double *__restrict__ part, double *__restrict__ Rinv,
-                                               int *__restrict__ act) {
-  __shared__ double Gs[RP][RP + 1];
-  __shared__ double Ls[RP][RP + 1];
-  __shared__ double col[RP];
+__global__ __launch_bounds__(256) void k_sum_gram(int nparts, const double *__restrict__ part,
+                                                  double *__restrict__ G) {
+  constexpr int EPB = 256 / SG;  // entries per workgroup
+  __shared__ double red[SG][EPB];
+  const int tid = threadIdx.x;
+  const int el = tid % EPB, g = tid / EPB;
+  const int e = blockIdx.x * EPB + el;
+  double s = 0.0;
+  if (e < RP * RP) {
+    for (int c = g; c < nparts; c += SG * 16) {
+      double v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int pc = c + SG * k;
+        v[k] = pc < nparts ? part[int64_t(pc) * RP * RP + e] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += v[k];
+    }
+  }
+  red[g][el] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = SG / 2; w > 0; w >>= 1) {
+    if (g < w) red[g][el] += red[g + w][el];
+    __syncthreads();
+  }
+  if (g == 0 && e < RP * RP) G[e] = red[0][el];
+}
+
+constexpr int CT = 1024;  // threads of the factorization kernel
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+
+// 1/x for finite x != 0: the hardware estimate refined by two Newton steps.
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  return y * fma(-x, y, 2.0);
+}
+
+// G = L L^T in one workgroup, one thread per matrix entry. Column j: the
+// pivot is the current A[j][j]; if it is <= 1e-12 of the original diagonal
+// (or that is <= 0) the column is dropped (L[:, j] = 0, L[j][j] = 1),
+// otherwise every entry (r, c), j < c <= r, takes
+//   A[r][c] -= (A[r][j] / sqrt(piv)) (A[c][j] / sqrt(piv)),
+// column j itself is scaled after the loop. Then X = L^{-1} by right-looking
+// forward substitution (step k: X[k][:] = B[k][:] / L[k][k], rows below
+// updated). Rinv[j][r] = X[r][j], i.e. Rinv = R^{-1} for R = L^T, with the
+// columns of dropped vectors zeroed; act[j] = 1 for kept columns.
+template <int RP>
+__global__ __launch_bounds__(CT) void k_chol(const double *__restrict__ G, double *__restrict__ Rinv,
+                                             int *__restrict__ act) {
+  __shared__ double A[RP][RP + 1];
+  __shared__ double B[RP][RP + 1];
+  __shared__ double diag[RP], rs[RP];
   __shared__ int keep[RP];
   const int tid = threadIdx.x;
-  for (int e = tid; e < RP * RP; e += 256) {
-    Gs[e / RP][e % RP] = strided_sum(part + e, nparts, int64_t(RP) * RP);
+  for (int e = tid; e < RP * RP; e += CT) {
+    const int r = e / RP, c = e % RP;
+    A[r][c] = G[e];
+    B[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  if (tid < RP) diag[tid] = G[tid * RP + tid];
+  __syncthreads();
+  for (int j = 0; j < RP; ++j) {
+    const double piv = A[j][j];
+    const bool ok = diag[j] > 0.0 && piv > 1e-12 * diag[j];
+    if (ok) {
+      const double rl = rsqrt_nr(piv);
+      for (int e = tid; e < RP * RP; e += CT) {
+        const int r = e / RP, c = e % RP;
+        if (c > j && c <= r) A[r][c] -= (A[r][j] * rl) * (A[c][j] * rl);
+      }
+    }
+    if (tid == 0) {
+      rs[j] = ok ? rsqrt_nr(piv) : 1.0;  // 1 / L[j][j]
+      keep[j] = ok ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  // L: column j scaled by rs[j] (diagonal: piv * rs = sqrt(piv)); dropped columns 0, diagonal 1
+  for (int e = tid; e < RP * RP; e += CT) {
+    const int r = e / RP, c = e % RP;
+    if (c < r) A[r][c] = keep[c] ? A[r][c] * rs[c] : 0.0;
+    if (c == r) A[r][c] = keep[c] ? A[r][c] * rs[c] : 1.0;
   }
   __syncthreads();
-  // The factorization and the inverse run in wavefront 0 alone: its lanes
-  // execute in lockstep, so an LDS fence orders a write by one lane before
-  // the reads of the others.
-  if (tid >= 64) return;
-  {
-    const int i = tid;  // lane i < RP owns row i
-    double a[RP];
-#pragma unroll
-    for (int k = 0; k < RP; ++k) a[k] = i < RP ? Gs[i][k] : 0.0;
-#pragma unroll
-    for (int j = 0; j < RP; ++j) {
-      const double djj = Gs[j][j];  // original diagonal
-      if (i == j) col[j] = a[j];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      const double piv = col[j];
-      const bool ok = djj > 0.0 && piv > 1e-12 * djj;
-      const double ljj = ok ? sqrt(piv) : 1.0;
-      const double lij = (i > j && i < RP && ok) ? a[j] / ljj : 0.0;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      if (i < RP) {
-        if (i == j) {
-          Ls[j][j] = ljj;
-          keep[j] = ok ? 1 : 0;
-        }
-        if (i > j) Ls[i][j] = lij;
-        col[i] = (i > j) ? lij : 0.0;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-#pragma unroll
-      for (int k = j + 1; k < RP; ++k) a[k] -= lij * col[k];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int k = 0; k < RP; ++k) {
+    const double dk = keep[k] ? rs[k] : 1.0;  // 1 / L[k][k]
+    for (int e = tid; e < RP * RP; e += CT) {
+      const int r = e / RP, j = e % RP;
+      if (r > k) B[r][j] -= A[r][k] * (B[k][j] * dk);
     }
+    __syncthreads();
   }
-  if (tid < RP) {
-    // column j = tid of X = L^{-1}: X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i]
-    const int j = tid;
-    double x[RP];
-#pragma unroll
-    for (int i = 0; i < RP; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= Ls[i][k] * x[k];
-      x[i] = (i >= j) ? v / Ls[i][i] : 0.0;
-    }
-    // Rinv[j][i] = X[i][j]; column i of Rinv zeroed if dropped
-#pragma unroll
-    for (int i = 0; i < RP; ++i) Rinv[j * RP + i] = keep[i] ? x[i] : 0.0;
-    act[j] = keep[j];
+  for (int e = tid; e < RP * RP; e += CT) {
+    const int j = e / RP, r = e % RP;
+    const double dr = keep[r] ? rs[r] : 1.0;
+    Rinv[e] = keep[r] ? B[r][j] * dr : 0.0;
   }
+  if (tid < RP) act[tid] = keep[tid];
 }
 
-// Q = Y Rinv (FP64, 64 rows per workgroup); optionally the next basis
-// X = W^1/2 Q in storage type T, and the chunk's partial Gram of Q.
-template <typename T, bool GRAM>
-__global__ __launch_bounds__(256) void k_apply_rinv(int64_t P, int rp, const double *__restrict__ Y,
-                                                     const double *__restrict__ Rinv, const double *__restrict__ w,
-                                                     double *__restrict__ Q, T *__restrict__ X,
-                                                     double *__restrict__ gpart) {
-  __shared__ double Ys[GROWS][65];
-  __shared__ double Ri[64][65];
-  const int64_t p0 = int64_t(blockIdx.x) * GROWS;
+// Q = Y Rinv in FP64 for ROWS rows per workgroup. With GRAM the rows' partial
+// Gram of Q is written (first pass of CholeskyQR2); otherwise the next basis
+// X = W^1/2 Q in storage type T.
+template <typename T, bool GRAM, int RP>
+__global__ __launch_bounds__(RT) void k_rows_apply(int64_t P, const double *__restrict__ Y,
+                                                    const double *__restrict__ Rinv, const double *__restrict__ sw,
+                                                    double *__restrict__ Q, T *__restrict__ X,
+                                                    double *__restrict__ gpart) {
+  constexpr int LD = RP + 1;
+  constexpr int NE = ROWS * RP / RT;
+  __shared__ double Ys[ROWS * LD];
+  __shared__ double Ri[RP * LD];
   const int tid = threadIdx.x;
-  for (int e = tid; e < rp * rp; e += 256) Ri[e / rp][e % rp] = Rinv[e];
-  for (int e = tid; e < GROWS * rp; e += 256) {
-    const int64_t p = p0 + e / rp;
-    Ys[e / rp][e % rp] = p < P ? Y[p * rp + e % rp] : 0.0;
+  const int64_t p0 = int64_t(blockIdx.x) * ROWS;
+  const int64_t base = p0 * RP, lim = P * RP;
+  for (int e = tid; e < RP * RP; e += RT) Ri[(e / RP) * LD + e % RP] = Rinv[e];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + RT * u;
+    Ys[(e / RP) * LD + e % RP] = base + e < lim ? Y[base + e] : 0.0;
   }
   __syncthreads();
-  double qv[GROWS * 64 / 256];
-  int cnt = 0;
-  for (int e = tid; e < GROWS * rp; e += 256, ++cnt) {
-    const int rr = e / rp, j = e % rp;
-    double s = 0.0;
-    for (int i = 0; i <= j; ++i) s += Ys[rr][i] * Ri[i][j];
-    qv[cnt] = s;
-    const int64_t p = p0 + rr;
+  double qv[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) qv[u] = 0.0;
+#pragma unroll 8
+  for (int i = 0; i < RP; ++i) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + RT * u;
+      qv[u] = fma(Ys[(e / RP) * LD + i], Ri[i * LD + e % RP], qv[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + RT * u;
+    const int64_t p = p0 + e / RP;
     if (p < P) {
-      Q[p * rp + j] = s;
-      if (X) X[p * rp + j] = T(sqrt(w[p]) * s);
+      Q[base + e] = qv[u];
+      if (!GRAM) X[base + e] = T(sw[p] * qv[u]);
     }
   }
   if (!GRAM) return;
   __syncthreads();
-  cnt = 0;
-  for (int e = tid; e < GROWS * rp; e += 256, ++cnt) Ys[e / rp][e % rp] = qv[cnt];
-  __syncthreads();
-  for (int e = tid; e < rp * rp; e += 256) {
-    const int a = e / rp, b = e % rp;
-    double s = 0.0;
-    for (int rr = 0; rr < GROWS; ++rr) s += Ys[rr][a] * Ys[rr][b];
-    gpart[int64_t(blockIdx.x) * rp * rp + e] = s;
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + RT * u;
+    Ys[(e / RP) * LD + e % RP] = (p0 + e / RP < P) ? qv[u] : 0.0;
   }
+  __syncthreads();
+  rows_gram<RP>(Ys, Ys, gpart + int64_t(blockIdx.x) * RP * RP, tid);
 }
 
-// One workgroup: B = sum of the partials restricted to the active columns,
-// symmetrized; cyclic Jacobi with round-robin ordering: the ne/2 disjoint
+constexpr int JT = 1024;  // threads of the Jacobi kernel
+
+// One workgroup: B = Q^T A Q restricted to the active columns, symmetrized; cyclic Jacobi with round-robin ordering: the ne/2 disjoint
 // rotations of a step are applied together, B' = J^T B J and V' = V J.
 // Eigenvalues sorted descending (stable); outputs the top k, their
-// eigenvectors in the rp basis, and FVE.
-__global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double *__restrict__ part,
-                                                 const int *__restrict__ act, int k, double *__restrict__ evals,
-                                                 double *__restrict__ fve, double *__restrict__ Uk) {
-  __shared__ double Bb[1][64][65];
-  __shared__ double Vb[1][64][65];
-  __shared__ double cs[32], sn[32];
-  __shared__ int pa[32], pb[32];
-  __shared__ int idx[64];
+// eigenvectors in the RP basis, and FVE.
+template <int RP>
+__global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, const int *__restrict__ act, int k,
+                                                double *__restrict__ evals, double *__restrict__ fve,
+                                                double *__restrict__ Uk) {
+  constexpr int LD = RP + 1;
+  __shared__ double Bb[RP * LD];
+  __shared__ double Vb[RP * LD];
+  __shared__ double cs[RP / 2], sn[RP / 2];
+  __shared__ int pa[RP / 2], pb[RP / 2];
+  __shared__ int idx[RP];
   __shared__ int n_s, ne_s, stop;
-  __shared__ double red_off[16], red_tot[16];
+  __shared__ double red_off[JT / 64], red_tot[JT / 64];
   const int tid = threadIdx.x;
   if (tid == 0) {
     int n = 0;
-    for (int j = 0; j < rp; ++j)
+    for (int j = 0; j < RP; ++j)
       if (act[j]) idx[n++] = j;
     n_s = n;
     ne_s = n + (n & 1);
   }
   __syncthreads();
   const int n = n_s, ne = ne_s;
-  for (int e = tid; e < ne * ne; e += blockDim.x) {
+  for (int e = tid; e < ne * ne; e += JT) {
     const int a = e / ne, b = e % ne;
-    double v = 0.0;
-    if (a < n && b < n) {
-      const int64_t o1 = int64_t(idx[a]) * rp + idx[b], o2 = int64_t(idx[b]) * rp + idx[a];
-      const double s1 = strided_sum(part + o1, nparts, int64_t(rp) * rp);
-      const double s2 = strided_sum(part + o2, nparts, int64_t(rp) * rp);
-      v = 0.5 * (s1 + s2);
-    }
-    Bb[0][a][b] = v;
-    Vb[0][a][b] = (a == b) ? 1.0 : 0.0;
+    Bb[a * LD + b] = (a < n && b < n) ? 0.5 * (G[idx[a] * RP + idx[b]] + G[idx[b] * RP + idx[a]]) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < ne * ne; e += JT) {
+    const int a = e / ne, b = e % ne;
+    Vb[a * LD + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int npair = ne / 2;
-  const int cur = 0;
   for (int sweep = 0; sweep < 60 && ne >= 2; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < ne * ne; e += blockDim.x) {
+    for (int e = tid; e < ne * ne; e += JT) {
       const int a = e / ne, b = e % ne;
-      const double v = Bb[cur][a][b] * Bb[cur][a][b];
+      const double v = Bb[a * LD + b] * Bb[a * LD + b];
       tot += v;
       if (a != b) off += v;
     }
@@ -387,7 +468,7 @@ __global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double
     __syncthreads();
     if (tid == 0) {
       double so = 0.0, st = 0.0;
-      for (int wv = 0; wv < int(blockDim.x / 64); ++wv) {
+      for (int wv = 0; wv < JT / 64; ++wv) {
         so += red_off[wv];
         st += red_tot[wv];
       }
@@ -405,12 +486,20 @@ __global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double
           a = (step + tid) % (ne - 1);
           b = (step - tid + ne - 1) % (ne - 1);
         }
-        const double apq = Bb[cur][a][b];
+        const double apq = Bb[a * LD + b];
         double c = 1.0, s = 0.0;
         if (apq != 0.0) {
-          const double tau = (Bb[cur][b][b] - Bb[cur][a][a]) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+          // t = tan of the rotation angle (the smaller root), c = cos, s = sin
+          const double tau = (Bb[b * LD + b] - Bb[a * LD + a]) * rcp_nr(2.0 * apq);
+          double t;
+          if (fabs(tau) > 1e150) {
+            t = 0.5 * rcp_nr(tau);
+          } else {
+            const double q = fma(tau, tau, 1.0);
+            const double r = rcp_nr(fabs(tau) + q * rsqrt_nr(q));
+            t = tau >= 0.0 ? r : -r;
+          }
+          c = rsqrt_nr(fma(t, t, 1.0));
           s = t * c;
         }
         pa[tid] = a;
@@ -423,39 +512,39 @@ __global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double
       // depends only on itself, B' = J1^T X J2 with J = [[c, s], [-s, c]];
       // V' = V J touches the two columns of one pair in one row.
       const int nblk = npair * npair;
-      for (int e = tid; e < nblk + ne * npair; e += blockDim.x) {
+      for (int e = tid; e < nblk + ne * npair; e += JT) {
         if (e < nblk) {
           const int m1 = e / npair, m2 = e % npair;
           const int a1 = pa[m1], b1 = pb[m1], a2 = pa[m2], b2 = pb[m2];
           const double c1 = cs[m1], s1 = sn[m1], c2 = cs[m2], s2 = sn[m2];
-          const double x00 = Bb[cur][a1][a2], x01 = Bb[cur][a1][b2];
-          const double x10 = Bb[cur][b1][a2], x11 = Bb[cur][b1][b2];
+          const double x00 = Bb[a1 * LD + a2], x01 = Bb[a1 * LD + b2];
+          const double x10 = Bb[b1 * LD + a2], x11 = Bb[b1 * LD + b2];
           const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
           const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
-          Bb[cur][a1][a2] = c2 * y00 - s2 * y01;
-          Bb[cur][a1][b2] = s2 * y00 + c2 * y01;
-          Bb[cur][b1][a2] = c2 * y10 - s2 * y11;
-          Bb[cur][b1][b2] = s2 * y10 + c2 * y11;
+          Bb[a1 * LD + a2] = c2 * y00 - s2 * y01;
+          Bb[a1 * LD + b2] = s2 * y00 + c2 * y01;
+          Bb[b1 * LD + a2] = c2 * y10 - s2 * y11;
+          Bb[b1 * LD + b2] = s2 * y10 + c2 * y11;
         } else {
           const int f = e - nblk;
           const int row = f / npair, m = f % npair;
           const int a = pa[m], b = pb[m];
           const double c = cs[m], s = sn[m];
-          const double va = Vb[cur][row][a], vb = Vb[cur][row][b];
-          Vb[cur][row][a] = c * va - s * vb;
-          Vb[cur][row][b] = s * va + c * vb;
+          const double va = Vb[row * LD + a], vb = Vb[row * LD + b];
+          Vb[row * LD + a] = c * va - s * vb;
+          Vb[row * LD + b] = s * va + c * vb;
         }
       }
       __syncthreads();
     }
   }
-  __shared__ int order[64];
+  __shared__ int order[RP];
   __shared__ double possum;
   if (tid < n) {
-    const double v = Bb[cur][tid][tid];
+    const double v = Bb[tid * LD + tid];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double u = Bb[cur][j][j];
+      const double u = Bb[j * LD + j];
       if (u > v || (u == v && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -463,24 +552,24 @@ __global__ __launch_bounds__(256) void k_jacobi(int rp, int nparts, const double
   if (tid == 0) {
     double s = 0.0;
     for (int j = 0; j < n; ++j)
-      if (Bb[cur][j][j] > 0.0) s += Bb[cur][j][j];
+      if (Bb[j * LD + j] > 0.0) s += Bb[j * LD + j];
     possum = s;
   }
   __syncthreads();
   if (tid == 0) {
     double cum = 0.0;
     for (int l = 0; l < k; ++l) {
-      const double v = l < n ? Bb[cur][order[l]][order[l]] : 0.0;
+      const double v = l < n ? Bb[order[l] * LD + order[l]] : 0.0;
       cum += v;
       evals[l] = v;
       fve[l] = possum > 0.0 ? cum / possum : 0.0;
     }
   }
-  for (int e = tid; e < rp * k; e += blockDim.x) Uk[e] = 0.0;
+  for (int e = tid; e < RP * k; e += JT) Uk[e] = 0.0;
   __syncthreads();
-  for (int e = tid; e < n * k; e += blockDim.x) {
+  for (int e = tid; e < n * k; e += JT) {
     const int a = e / k, l = e % k;
-    if (l < n) Uk[int64_t(idx[a]) * k + l] = Vb[cur][a][order[l]];
+    if (l < n) Uk[int64_t(idx[a]) * k + l] = Vb[a * LD + order[l]];
   }
 }
 
@@ -567,16 +656,14 @@ __global__ __launch_bounds__(256) void k_sign_write(int64_t P, int nblk, const d
 
 inline unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
 
-template <int RP>
-void launch_chol(fpca_context *ctx, int nparts, const double *part, double *Rinv, int *act) {
-  hipLaunchKernelGGL(k_chol<RP>, dim3(1), dim3(256), 0, ctx->stream, nparts, part, Rinv, act);
+__global__ void k_sqrt(int64_t P, const double *__restrict__ w, double *__restrict__ sw) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < P) sw[p] = sqrt(w[p]);
 }
 
-template <typename T>
-int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k,
-             int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
-  const int r = k + oversample;
-  const int rp = ((r + 15) / 16) * 16;
+template <typename T, int RP>
+int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k, int r,
+            int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
   const bool f32 = sizeof(T) == 4;
   // K split of the panel product: enough workgroups to fill the chip
   const int64_t colblocks = (P + 63) / 64;
@@ -584,30 +671,32 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
   if (nsplit < 1) nsplit = 1;
   int64_t kchunk = ((P + nsplit - 1) / nsplit + 31) / 32 * 32;
   nsplit = (P + kchunk - 1) / kchunk;
-  const int64_t ngram = (P + GROWS - 1) / GROWS;
+  const int64_t ngram = (P + ROWS - 1) / ROWS;
   const int64_t nphi = (P + 255) / 256;
-  size_t need = carve_bytes(P, 8) + carve_bytes(P * rp, sizeof(T)) + 3 * carve_bytes(P * rp, 8) +
-                carve_bytes(ngram * rp * rp, 8) + carve_bytes(rp * rp, 8) + carve_bytes(rp, 4) +
-                carve_bytes(rp * k, 8) + 2 * carve_bytes(k, 8) + carve_bytes(P * k, 8) +
-                carve_bytes(nphi * k * 3, 8);
-  need += f32 ? carve_bytes(nsplit * P * rp, 4) : carve_bytes(P * rp, 8);
+  size_t need = 2 * carve_bytes(P, 8) + carve_bytes(P * RP, sizeof(T)) + 3 * carve_bytes(P * RP, 8) +
+                carve_bytes(ngram * RP * RP, 8) + 2 * carve_bytes(RP * RP, 8) + carve_bytes(RP, 4) +
+                carve_bytes(RP * k, 8) +
+                2 * carve_bytes(k, 8) + carve_bytes(P * k, 8) + carve_bytes(nphi * k * 3, 8);
+  need += f32 ? carve_bytes(nsplit * P * RP, 4) : carve_bytes(P * RP, 8);
   if (int rc = ws_reserve(ctx, need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
   double *w = cv.take<double>(P);
-  T *X = cv.take<T>(P * rp);
-  double *Y = cv.take<double>(P * rp);
-  double *Q = cv.take<double>(P * rp);
-  double *Z = cv.take<double>(P * rp);
-  double *gpart = cv.take<double>(ngram * rp * rp);
-  double *Rinv = cv.take<double>(rp * rp);
-  int *act = cv.take<int>(rp);
-  double *Uk = cv.take<double>(rp * k);
+  double *sw = cv.take<double>(P);
+  T *X = cv.take<T>(P * RP);
+  double *Y = cv.take<double>(P * RP);
+  double *Q = cv.take<double>(P * RP);
+  double *Z = cv.take<double>(P * RP);
+  double *gpart = cv.take<double>(ngram * RP * RP);
+  double *G = cv.take<double>(RP * RP);
+  double *Rinv = cv.take<double>(RP * RP);
+  int *act = cv.take<int>(RP);
+  double *Uk = cv.take<double>(RP * k);
   double *ev_d = cv.take<double>(k);
   double *fve_d = cv.take<double>(k);
   double *phi = cv.take<double>(P * k);
   double *red = cv.take<double>(nphi * k * 3);
-  float *part = f32 ? cv.take<float>(nsplit * P * rp) : nullptr;
-  double *Yraw = f32 ? nullptr : cv.take<double>(P * rp);
+  float *part = f32 ? cv.take<float>(nsplit * P * RP) : nullptr;
+  double *Yraw = f32 ? nullptr : cv.take<double>(P * RP);
 
   if (quad_w) {
     FPCA_HIP(hipMemcpyAsync(w, quad_w, sizeof(double) * P, hipMemcpyDeviceToDevice, ctx->stream));
@@ -617,63 +706,57 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
     hipLaunchKernelGGL(k_default_w, dim3(nb(P)), dim3(256), 0, ctx->stream, P, wv, grid->mask, w);
     FPCA_LAUNCH_CHECK("default_w");
   }
-  hipLaunchKernelGGL(k_test_matrix<T>, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, seed, P, r, rp, w, X);
+  hipLaunchKernelGGL(k_sqrt, dim3(nb(P)), dim3(256), 0, ctx->stream, P, w, sw);
+  FPCA_LAUNCH_CHECK("sqrt_w");
+  hipLaunchKernelGGL(k_test_matrix<T>, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, seed, P, r, RP, w, X);
   FPCA_LAUNCH_CHECK("test_matrix");
 
-  // Y (or Z) = W^1/2 Gamma X, then the partial Gram (MODE 1: of itself, MODE 2: Q^T Y)
+  // Y (or Z) = W^1/2 Gamma X, then the partial Gram into gA (MODE 1: of itself, MODE 2: Q^T Y)
   auto product = [&](double *out, int mode) -> int {
     if constexpr (sizeof(T) == 4) {
       dim3 grd((unsigned)colblocks, (unsigned)nsplit);
       const bool vec = (P % 4 == 0) && ((reinterpret_cast<uintptr_t>(gamma) & 15) == 0);
-#define PANEL(RB)                                                                                          \
-  if (vec)                                                                                                 \
-    hipLaunchKernelGGL((k_panel_f32<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,   \
-                       (const float *)X, kchunk, part);                                                    \
-  else                                                                                                     \
-    hipLaunchKernelGGL((k_panel_f32<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,  \
-                       (const float *)X, kchunk, part);
-      switch (rp / 16) {
-        case 1: PANEL(1) break;
-        case 2: PANEL(2) break;
-        case 3: PANEL(3) break;
-        default: PANEL(4) break;
-      }
-#undef PANEL
+      constexpr int RB = RP / 16;
+      if (vec)
+        hipLaunchKernelGGL((k_panel_f32<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                           (const float *)X, kchunk, part);
+      else
+        hipLaunchKernelGGL((k_panel_f32<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                           (const float *)X, kchunk, part);
       FPCA_LAUNCH_CHECK("panel_f32");
     } else {
-      hipLaunchKernelGGL(k_panel_f64, dim3(nb(P * rp)), dim3(256), 0, ctx->stream, P, rp, (const double *)gamma,
+      hipLaunchKernelGGL(k_panel_f64, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, P, RP, (const double *)gamma,
                          (const double *)X, Yraw);
       FPCA_LAUNCH_CHECK("panel_f64");
     }
     if (mode == 2)
-      hipLaunchKernelGGL(k_reduce_gram<2>, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, int(nsplit), part,
-                         Yraw, w, Q, out, gpart);
+      hipLaunchKernelGGL((k_rows_gram<2, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, int(nsplit), part,
+                         Yraw, sw, Q, out, gpart);
     else
-      hipLaunchKernelGGL(k_reduce_gram<1>, dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, int(nsplit), part,
-                         Yraw, w, Q, out, gpart);
-    FPCA_LAUNCH_CHECK("reduce_gram");
+      hipLaunchKernelGGL((k_rows_gram<1, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, int(nsplit), part,
+                         Yraw, sw, Q, out, gpart);
+    FPCA_LAUNCH_CHECK("rows_gram");
     return FPCA_OK;
   };
-  auto chol = [&]() -> int {
-    switch (rp) {
-      case 16: launch_chol<16>(ctx, int(ngram), gpart, Rinv, act); break;
-      case 32: launch_chol<32>(ctx, int(ngram), gpart, Rinv, act); break;
-      case 48: launch_chol<48>(ctx, int(ngram), gpart, Rinv, act); break;
-      default: launch_chol<64>(ctx, int(ngram), gpart, Rinv, act); break;
-    }
+  // G = sum of the partial Gram matrices; Cholesky factor and R^-1 of G
+  auto factor = [&]() -> int {
+    hipLaunchKernelGGL(k_sum_gram<RP>, dim3(unsigned((RP * RP + 256 / SG - 1) / (256 / SG))), dim3(256), 0,
+                       ctx->stream, int(ngram), gpart, G);
+    FPCA_LAUNCH_CHECK("sum_gram");
+    hipLaunchKernelGGL(k_chol<RP>, dim3(1), dim3(CT), 0, ctx->stream, G, Rinv, act);
     FPCA_LAUNCH_CHECK("chol");
     return FPCA_OK;
   };
-  // CholeskyQR2 of Y (whose partial Gram is already in gpart): Y -> Z -> Q, X.
+  // CholeskyQR2 of Y (whose partial Gram is in gpart): Y -> Z -> Q, X.
   auto cholqr2 = [&]() -> int {
-    if (int rc = chol()) return rc;
-    hipLaunchKernelGGL((k_apply_rinv<T, true>), dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, Y, Rinv, w, Z,
-                       (T *)nullptr, gpart);
-    FPCA_LAUNCH_CHECK("apply_rinv");
-    if (int rc = chol()) return rc;
-    hipLaunchKernelGGL((k_apply_rinv<T, false>), dim3(unsigned(ngram)), dim3(256), 0, ctx->stream, P, rp, Z, Rinv, w,
-                       Q, X, (double *)nullptr);
-    FPCA_LAUNCH_CHECK("apply_rinv");
+    if (int rc = factor()) return rc;
+    hipLaunchKernelGGL((k_rows_apply<T, true, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, Y, Rinv, sw,
+                       Z, (T *)nullptr, gpart);
+    FPCA_LAUNCH_CHECK("rows_apply");
+    if (int rc = factor()) return rc;
+    hipLaunchKernelGGL((k_rows_apply<T, false, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, Z, Rinv,
+                       sw, Q, X, (double *)nullptr);
+    FPCA_LAUNCH_CHECK("rows_apply");
     return FPCA_OK;
   };
 
@@ -684,9 +767,13 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
     if (int rc = cholqr2()) return rc;
   }
   if (int rc = product(Z, 2)) return rc;  // Z = A Q and the partials of Q^T Z
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, ctx->stream, rp, int(ngram), gpart, act, k, ev_d, fve_d, Uk);
+  hipLaunchKernelGGL(k_sum_gram<RP>, dim3(unsigned((RP * RP + 256 / SG - 1) / (256 / SG))), dim3(256), 0, ctx->stream,
+                     int(ngram), gpart, G);
+  FPCA_LAUNCH_CHECK("sum_gram");
+  hipLaunchKernelGGL(k_jacobi<RP>, dim3(1), dim3(JT), 0, ctx->stream, G, act, k, ev_d, fve_d, Uk);
   FPCA_LAUNCH_CHECK("jacobi");
-  hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, rp, k, Q, Uk, w, phi, red);
+  hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, RP, k, Q, Uk, w, phi,
+                     red);
   FPCA_LAUNCH_CHECK("phi");
   hipLaunchKernelGGL(k_sign_write<T>, dim3(unsigned(k)), dim3(256), 0, ctx->stream, P, int(nphi), phi, red, efuns);
   FPCA_LAUNCH_CHECK("sign_write");
@@ -699,6 +786,18 @@ int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma
     if (fve_h) fve_h[l] = hb[k + l];
   }
   return FPCA_OK;
+}
+
+template <typename T>
+int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k,
+             int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
+  const int r = k + oversample;
+  switch ((r + 15) / 16) {
+    case 1: return eig_run<T, 16>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
+    case 2: return eig_run<T, 32>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
+    case 3: return eig_run<T, 48>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
+    default: return eig_run<T, 64>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
+  }
 }
 
 }  // namespace

@@ -14,14 +14,39 @@ constexpr int LDP = TB + 16;  // padded LDS row (bank spread for the 4 K-rows of
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline void tile_of(int id, int nb, int *bi, int *bj) {
-  int r = 0;
-  while (id >= nb - r) {
-    id -= nb - r;
-    ++r;
+constexpr int XCDS = 8;  // workgroups are dispatched round-robin over the XCDs
+constexpr int BAND = 8;  // tile columns per band of the schedule
+
+// Tile (bi, bj), bi <= bj, of workgroup `id`; false for a padding workgroup.
+// Workgroup id runs on XCD id % 8, and each XCD takes a contiguous run of
+// `per` tiles in band order (bands of 8 tile columns; within a band, rows top
+// to bottom with the band's columns of a row together, then the band's
+// diagonal triangle), so the tiles sharing one L2 cover a compact block of
+// rows and columns and reuse each other's operand slabs.
+__device__ inline bool tile_of(int id, int nb, int per, int *bi, int *bj) {
+  int t = (id % XCDS) * per + id / XCDS;
+  for (int J0 = 0; J0 < nb; J0 += BAND) {
+    const int w = min(BAND, nb - J0);
+    const int full = J0 * w;  // rows 0 .. J0-1, w columns each
+    const int cnt = full + w * (w + 1) / 2;
+    if (t < cnt) {
+      if (t < full) {
+        *bi = t / w;
+        *bj = J0 + t % w;
+      } else {
+        int r = t - full, ii = 0;
+        while (r >= w - ii) {
+          r -= w - ii;
+          ++ii;
+        }
+        *bi = J0 + ii;
+        *bj = J0 + ii + r;
+      }
+      return true;
+    }
+    t -= cnt;
   }
-  *bi = r;
-  *bj = r + id;
+  return false;
 }
 
 // bf16 split of an FP32 value: hi = round-to-nearest-even bf16(x), lo = bf16(x - hi).
@@ -33,17 +58,15 @@ __device__ inline unsigned short bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-// FP32 operands; PREC 1: v_mfma_f32_16x16x4_f32 on FP32 values;
-// PREC 2: each operand split into bf16 hi/lo, products hi*hi + hi*lo + lo*hi
-// accumulated in FP32 on v_mfma_f32_16x16x16_bf16.
-template <bool VEC4, int PREC>
+// FP32 operands on v_mfma_f32_16x16x4_f32.
+template <bool VEC4>
 __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, int64_t K, int64_t N,
                                                    float *__restrict__ C, int64_t ldc, float alpha,
-                                                   int zero_diag, int nb) {
+                                                   int zero_diag, int nb, int per) {
   __shared__ float As[TK][LDP];
   __shared__ float Bs[TK][LDP];
   int bi, bj;
-  tile_of(blockIdx.x, nb, &bi, &bj);
+  if (!tile_of(blockIdx.x, nb, per, &bi, &bj)) return;  // uniform per workgroup
   const bool diag_tile = (bi == bj);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -98,48 +121,18 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
     }
     __syncthreads();
     const float(*Bsrc)[LDP] = diag_tile ? As : Bs;
-    if (PREC == 1) {
 #pragma unroll
-      for (int kk = 0; kk < TK; kk += 4) {
-        float a[4], b[4];
-        const int krow = kk + (lane >> 4);
+    for (int kk = 0; kk < TK; kk += 4) {
+      float a[4], b[4];
+      const int krow = kk + (lane >> 4);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As[krow][wm * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i) a[i] = As[krow][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = Bsrc[krow][wn * 64 + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      // One 16x16x16 bf16 MFMA covers the whole 16-row K slab: lane supplies
-      // 4 consecutive K values (rows 4*(lane/16) .. +3) of its row/column.
-      typedef short short4_t __attribute__((ext_vector_type(4)));
-      short4_t ahi[4], alo[4], bhi[4], blo[4];
-      const int kb = 4 * (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float x = As[kb + e][wm * 64 + i * 16 + (lane & 15)];
-          unsigned short h = bf16_rne(x);
-          ahi[i][e] = (short)h;
-          alo[i][e] = (short)bf16_rne(x - bf16_to_f32(h));
-          float z = Bsrc[kb + e][wn * 64 + i * 16 + (lane & 15)];
-          unsigned short g = bf16_rne(z);
-          bhi[i][e] = (short)g;
-          blo[i][e] = (short)bf16_rne(z - bf16_to_f32(g));
-        }
-      }
+      for (int j = 0; j < 4; ++j) b[j] = Bsrc[krow][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -197,12 +190,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __global__ __launch_bounds__(256) void k_syrk_bf16x3(const unsigned short *__restrict__ Th,
                                                       const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
                                                       float *__restrict__ C, int64_t ldc, float alpha, int zero_diag,
-                                                      int nb) {
+                                                      int nb, int per) {
   constexpr int BK = 32;
   constexpr int LR = BK + 8;  // padded LDS row in bf16 elements (80 bytes)
   __shared__ __attribute__((aligned(16))) unsigned short S[2][4][TB][LR];  // [buf][Ah Al Bh Bl][row][k]
   int bi, bj;
-  tile_of(blockIdx.x, nb, &bi, &bj);
+  if (!tile_of(blockIdx.x, nb, per, &bi, &bj)) return;  // uniform per workgroup
   const bool diag_tile = (bi == bj);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -345,8 +338,10 @@ __global__ __launch_bounds__(256) void k_gram_valu(const Tin *__restrict__ A, in
 int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, int64_t ldc, float alpha,
              bool zero_diag, int prec) {
   if (N <= 0) return FPCA_OK;
-  int nb = int((N + TB - 1) / TB);
-  int tiles = nb * (nb + 1) / 2;
+  const int nb = int((N + TB - 1) / TB);
+  const int tiles = nb * (nb + 1) / 2;
+  const int per = (tiles + XCDS - 1) / XCDS;  // tiles per XCD
+  const unsigned grid = unsigned(per) * XCDS;
   bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   if (prec == FPCA_PREC_BF16X3) {
     const int64_t Kp = ((K + 31) / 32) * 32;
@@ -359,15 +354,15 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
       hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
       FPCA_LAUNCH_CHECK("split_t");
     }
-    hipLaunchKernelGGL(k_syrk_bf16x3, dim3(tiles), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
-                       int(zero_diag), nb);
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3(grid), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
+                       int(zero_diag), nb, per);
   } else {
     if (vec)
-      hipLaunchKernelGGL((k_syrk_f32<true, 1>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
-                         int(zero_diag), nb);
+      hipLaunchKernelGGL((k_syrk_f32<true>), dim3(grid), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb, per);
     else
-      hipLaunchKernelGGL((k_syrk_f32<false, 1>), dim3(tiles), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
-                         int(zero_diag), nb);
+      hipLaunchKernelGGL((k_syrk_f32<false>), dim3(grid), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,
+                         int(zero_diag), nb, per);
   }
   FPCA_LAUNCH_CHECK("syrk_f32");
   return FPCA_OK;

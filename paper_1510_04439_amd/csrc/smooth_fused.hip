@@ -248,22 +248,45 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
   int xmax = int(min(int64_t(P - 1), t0 + TW - 1) / M2);
   const int64_t PP = P * P;
 
-  // static per-lane factors of the analytic weight moments
-  double Af[15], Bf[15];
+  // static per-lane factors of the analytic weight moments: window sums
+  // W[e] of the s2, t1 and t2 coordinates and the diagonal-overlap sums
+  // Dg[ab] of the second grid coordinate at (s2, t2)
+  double ws2[3], wt1[3], wt2[3], dg2[6];
   {
     const int Mm = tab.Mmax;
     const double *W1 = tab.W, *W2 = tab.W + 3 * Mm;
     const double *D2 = tab.Dg + 6 * int64_t(Mm) * Mm;
     const int s2 = lane < M2 ? lane : 0;
-    // e = (a1, a2, b1, b2) in moment order
-    const int E[15][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
-                          {2, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {1, 0, 0, 1}, {0, 2, 0, 0},
-                          {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 2, 0}, {0, 0, 1, 1}, {0, 0, 0, 2}};
 #pragma unroll
-    for (int q = 0; q < 15; ++q) {
-      Af[q] = W2[E[q][1] * Mm + s2] * W1[E[q][2] * Mm + (t1 < 0 ? 0 : t1)] * W2[E[q][3] * Mm + t2];
-      Bf[q] = D2[(int64_t(ab_index(E[q][1], E[q][3])) * Mm + s2) * Mm + t2];
+    for (int e = 0; e < 3; ++e) {
+      ws2[e] = W2[e * Mm + s2];
+      wt1[e] = W1[e * Mm + (t1 < 0 ? 0 : t1)];
+      wt2[e] = W2[e * Mm + t2];
     }
+#pragma unroll
+    for (int ab = 0; ab < 6; ++ab) dg2[ab] = D2[(int64_t(ab) * Mm + s2) * Mm + t2];
+  }
+  // Tensor-product design (windows of s and t that share no node): with
+  // per-coordinate window sums W0, W1, W2, m = W1/W0, e = W2/W0, v = e - m^2,
+  // the fit's centered second-moment matrix is diagonal and
+  //   b0 = [T0 (1 + sum_k m_k^2/v_k) - sum_k (m_k/v_k) T1_k] / S0,
+  // with the pivots of the scaled system equal to v_k / e_k. The s2, t1, t2
+  // parts are fixed per lane; the s1 part is added per row.
+  double tz_c = 0.0, tz_a[3] = {0.0, 0.0, 0.0}, tz_inv = 0.0;
+  bool tz_ok = true;
+  {
+    const double *tb[3] = {ws2, wt1, wt2};
+    double prod = c0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double w0 = tb[k][0], mk = tb[k][1] / w0, ek = tb[k][2] / w0;
+      const double vk = ek - mk * mk;
+      tz_ok = tz_ok && ek > 0.0 && vk >= 1e-10 * ek;
+      tz_a[k] = mk / vk;
+      tz_c += mk * tz_a[k];
+      prod *= w0;
+    }
+    tz_inv = 1.0 / prod;
   }
 
   float win[NU][W];
@@ -321,22 +344,41 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
     }
     const int Mm = tab.Mmax;
     const double *W1 = tab.W;
-    const double *D1 = tab.Dg;
     const double w0 = W1[0 * Mm + x], w1 = W1[1 * Mm + x], w2 = W1[2 * Mm + x];
-    const int tt1 = t1;
-    auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
-    const int E1[15][2] = {{0, 0}, {1, 0}, {0, 0}, {0, 1}, {0, 0}, {2, 0}, {1, 0}, {1, 1},
-                           {1, 0}, {0, 0}, {0, 1}, {0, 0}, {0, 2}, {0, 1}, {0, 0}};
-#pragma unroll
-    for (int q = 0; q < 15; ++q) {
-      const double wa = E1[q][0] == 0 ? w0 : (E1[q][0] == 1 ? w1 : w2);
-      m[q] = c0 * (wa * Af[q] - d1(E1[q][0], E1[q][1]) * Bf[q]);
-    }
     if (lane >= M2) continue;
     const int64_t p = int64_t(x) * M2 + lane;
     if (p > t) continue;
     int8_t st;
-    double b0 = wls_b0<4>(m, &st);
+    double b0;
+    if (abs(x - t1) > 2 * R || abs(lane - t2) > 2 * R) {
+      const double r0 = 1.0 / w0, mx = w1 * r0, ex = w2 * r0, vx = ex - mx * mx;
+      const double inv = tz_inv * r0;
+      if (tz_ok && ex > 0.0 && vx >= 1e-10 * ex) {
+        const double ax = mx / vx;
+        b0 = (m[15] * (1.0 + tz_c + mx * ax) - ax * m[16] - tz_a[0] * m[17] - tz_a[1] * m[18] - tz_a[2] * m[19]) *
+             inv;
+        st = FPCA_STATUS_OK;
+      } else {
+        b0 = m[15] * inv;
+        st = FPCA_STATUS_FALLBACK;
+      }
+    } else {
+      // the diagonal exclusion couples s and t: full system
+      const double *D1 = tab.Dg;
+      const int tt1 = t1;
+      auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
+      // moment q has u-exponents (a1, a2, b1, b2) in (s1, s2, t1, t2)
+      const int E[15][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
+                            {2, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {1, 0, 0, 1}, {0, 2, 0, 0},
+                            {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 2, 0}, {0, 0, 1, 1}, {0, 0, 0, 2}};
+      const double wx[3] = {w0, w1, w2};
+#pragma unroll
+      for (int q = 0; q < 15; ++q) {
+        const double af = ws2[E[q][1]] * wt1[E[q][2]] * wt2[E[q][3]];
+        m[q] = c0 * (wx[E[q][0]] * af - d1(E[q][0], E[q][2]) * dg2[ab_index(E[q][1], E[q][3])]);
+      }
+      b0 = wls_b0<4>(m, &st);
+    }
     if (mu) b0 -= double(mu[p]) * double(mu[t]);
     if (mask && (!mask[p] || !mask[t])) b0 = 0.0;
     const float v = float(b0);

@@ -93,9 +93,11 @@ def fit(h: B.Handle, dd: DeviceData, bufs: FitBuffers, h_mean: float, h_cov: flo
     mu_cov = mean_on_cov_grid(dd, bufs)
     if analytic_C:
         C = None
+        # common grid: the pair weights are c_uniform (1 - delta) and are not materialized
+        W = None if dd.design == B.FPCA_COMMON_GRID else bufs.extra.setdefault("Cscratch",
+                                                                             bufs.G.new_empty(bufs.G.shape))
         B.fpca_bin(h, dd.grid_cov, B.FPCA_BIN_COV, dd.design, dd.dtype, prec, dd.n, dd.offsets, dd.t,
-                   dd.y, None, 0, bufs.extra.setdefault("Cscratch", bufs.G.new_empty(bufs.G.shape)),
-                   bufs.G)
+                   dd.y, None, 0, W, bufs.G)
     else:
         C = bufs.C
         B.fpca_bin(h, dd.grid_cov, B.FPCA_BIN_COV, dd.design, dd.dtype, prec, dd.n, dd.offsets, dd.t,

@@ -248,24 +248,40 @@ def summarize(rows):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--train-start", type=int, default=0, help="index of the first training dataset")
     ap.add_argument("--n-test", type=int, default=300)
     ap.add_argument("--n-scale", type=float, default=1.0)
     ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--labels-out", default=None, help="save the training labels (npz) and stop")
+    ap.add_argument("--labels-in", default=None,
+                    help="comma-separated label files from --labels-out to train on (no labelling)")
     ap.add_argument("--out", default="gpurun_out/bw_surrogate.npz")
     ap.add_argument("--report", default="gpurun_out/bw_surrogate.json")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available()
     h = B.Handle(0)
-    log(f"labelling {args.n_train} training datasets")
-    ftr, ltr, str_, qtr, mtr = label_many(h, "train", args.n_train, args.n_scale)
+    if args.labels_in:
+        parts = [np.load(f) for f in args.labels_in.split(",")]
+        ftr = np.concatenate([z["feats"] for z in parts])
+        ltr = np.concatenate([z["labels"] for z in parts])
+        log(f"loaded {len(ltr)} labelled training datasets")
+    else:
+        log(f"labelling {args.n_train} training datasets from index {args.train_start}")
+        ftr, ltr, str_, qtr, mtr = label_many(h, "train", args.n_train, args.n_scale, start=args.train_start)
+        if args.labels_out:
+            np.savez(args.labels_out, feats=ftr, labels=ltr, scores=str_, qtot=qtr, meta=mtr,
+                     start=args.train_start, n_scale=args.n_scale)
+            log(f"saved {args.labels_out}")
+            h.close()
+            return
     log("training")
     model = train(h, ftr, np.log(ltr), steps=args.steps)
     model.save(args.out)
     log(f"saved {args.out}; evaluating on {args.n_test} held-out datasets")
     rows = evaluate(h, model, "test", args.n_test, args.n_scale)
     summ = summarize(rows)
-    summ.update(n_train=args.n_train, n_scale=args.n_scale, steps=args.steps, h_grid=H_GRID.tolist(),
+    summ.update(n_train=len(ltr), n_scale=args.n_scale, steps=args.steps, h_grid=H_GRID.tolist(),
                 label_log_h_sd=float(np.std(np.log(ltr))))
     with open(args.report, "w") as fh:
         json.dump(dict(summary=summ, rows=rows), fh)

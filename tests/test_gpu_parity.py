@@ -131,29 +131,40 @@ def test_bin_cov_parity(torch, F, h, d, M, dt, nf, bf):
             assert np.array_equal(host(cnt), rn)
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x3", 1e-4)])
-def test_bin_cov_common_grid(torch, F, h, prec, tol):
-    _say(f"bin_cov common {prec}")
+@pytest.mark.parametrize("prec,tol,M", [("f32", 1e-5, (20, 13)), ("bf16x3", 1e-4, (20, 13)), ("f32", 1e-5, (7, 9))])
+def test_bin_cov_common_grid(torch, F, h, prec, tol, M):
+    """Common-grid binning: Gram product with the diagonal removed, the pair
+    weights (or none when weights = NULL), and the mean sums and sums of
+    squares (column sums over row chunks with a ragged last chunk; P = 63
+    leaves a partial group of four columns)."""
+    _say(f"bin_cov common {prec} M={M}")
     rng = np.random.default_rng(7)
-    M = (20, 13)
-    P = 260
+    P = int(np.prod(M))
     n = 333
     Y = rng.standard_normal((n, P)).astype(np.float32)
     C = torch.empty(P, P, dtype=torch.float32, device="cuda:0")
     G = torch.empty_like(C)
-    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, F.FPCA_F32,
-               F.FPCA_PREC_F32 if prec == "f32" else F.FPCA_PREC_BF16X3, n, None, None, dev(torch, Y), None, 0,
-               C, G)
+    G2 = torch.empty_like(C)
+    pr = F.FPCA_PREC_F32 if prec == "f32" else F.FPCA_PREC_BF16X3
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, F.FPCA_F32, pr, n, None, None, dev(torch, Y), None,
+               0, C, G)
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, F.FPCA_F32, pr, n, None, None, dev(torch, Y), None,
+               0, None, G2)
     c = torch.empty(P, dtype=torch.float32, device="cuda:0")
     s = torch.empty_like(c)
+    s2 = torch.empty_like(c)
     F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_MEAN, F.FPCA_COMMON_GRID, F.FPCA_F32, F.FPCA_PREC_F32, n, None, None,
-               dev(torch, Y), None, 0, c, s)
+               dev(torch, Y), None, 0, c, s, s2)
     h.sync()
-    rc, rs, rC, rG = oracle.bin_common_grid(Y.astype(np.float64))
+    Y64 = Y.astype(np.float64)
+    rc, rs, rC, rG = oracle.bin_common_grid(Y64)
+    rs2 = oracle.bin_common_grid(Y64 ** 2)[1]
     assert normwise_rel(host(C), rC) < 1e-7
     assert normwise_rel(host(G), rG) < tol
+    assert np.array_equal(host(G), host(G2))
     assert np.all(np.diag(host(G)) == 0)
     assert normwise_rel(host(c), rc) < 1e-7 and normwise_rel(host(s), rs) < 1e-5
+    assert normwise_rel(host(s2), rs2) < 1e-5
 
 
 def test_domain_error_reported(torch, F, h):
