@@ -412,9 +412,42 @@ __global__ __launch_bounds__(RT) void k_rows_apply(int64_t P, const double *__re
 
 constexpr int JT = 1024;  // threads of the Jacobi kernel
 
-// One workgroup: B = Q^T A Q restricted to the active columns, symmetrized; cyclic Jacobi with round-robin ordering: the ne/2 disjoint
-// rotations of a step are applied together, B' = J^T B J and V' = V J.
-// Eigenvalues sorted descending (stable); outputs the top k, their
+// Rotation (c, s) that annihilates B[a][b] of the symmetric matrix in Bm
+// (row stride LD): t = tan of the smaller angle, c = cos, s = sin.
+__device__ inline void jacobi_rot(const double *Bm, int LD, int a, int b, double *c, double *s) {
+  const double apq = Bm[a * LD + b];
+  *c = 1.0;
+  *s = 0.0;
+  if (apq == 0.0) return;
+  const double tau = (Bm[b * LD + b] - Bm[a * LD + a]) * rcp_nr(2.0 * apq);
+  double t;
+  if (fabs(tau) > 1e150) {
+    t = 0.5 * rcp_nr(tau);
+  } else {
+    const double q = fma(tau, tau, 1.0);
+    const double r = rcp_nr(fabs(tau) + q * rsqrt_nr(q));
+    t = tau >= 0.0 ? r : -r;
+  }
+  *c = rsqrt_nr(fma(t, t, 1.0));
+  *s = t * *c;
+}
+
+// Round-robin pairing of ne (even) indices at a step: pair 0 = (ne-1, step),
+// pair m > 0 = ((step + m) mod (ne-1), (step - m) mod (ne-1)).
+__device__ inline void rr_pair(int ne, int step, int m, int *a, int *b) {
+  if (m == 0) {
+    *a = ne - 1;
+    *b = step;
+  } else {
+    *a = (step + m) % (ne - 1);
+    *b = (step - m + ne - 1) % (ne - 1);
+  }
+}
+
+// One workgroup: B = Q^T A Q restricted to the active columns, symmetrized;
+// cyclic Jacobi with round-robin ordering: the ne/2 disjoint rotations of a
+// step are computed first, then applied together in place, B' = J^T B J and
+// V' = V J. Eigenvalues sorted descending (stable); outputs the top k, their
 // eigenvectors in the RP basis, and FVE.
 template <int RP>
 __global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, const int *__restrict__ act, int k,
@@ -441,10 +474,6 @@ __global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, con
   for (int e = tid; e < ne * ne; e += JT) {
     const int a = e / ne, b = e % ne;
     Bb[a * LD + b] = (a < n && b < n) ? 0.5 * (G[idx[a] * RP + idx[b]] + G[idx[b] * RP + idx[a]]) : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < ne * ne; e += JT) {
-    const int a = e / ne, b = e % ne;
     Vb[a * LD + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -479,29 +508,9 @@ __global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, con
     for (int step = 0; step < ne - 1; ++step) {
       if (tid < npair) {
         int a, b;
-        if (tid == 0) {
-          a = ne - 1;
-          b = step;
-        } else {
-          a = (step + tid) % (ne - 1);
-          b = (step - tid + ne - 1) % (ne - 1);
-        }
-        const double apq = Bb[a * LD + b];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          // t = tan of the rotation angle (the smaller root), c = cos, s = sin
-          const double tau = (Bb[b * LD + b] - Bb[a * LD + a]) * rcp_nr(2.0 * apq);
-          double t;
-          if (fabs(tau) > 1e150) {
-            t = 0.5 * rcp_nr(tau);
-          } else {
-            const double q = fma(tau, tau, 1.0);
-            const double r = rcp_nr(fabs(tau) + q * rsqrt_nr(q));
-            t = tau >= 0.0 ? r : -r;
-          }
-          c = rsqrt_nr(fma(t, t, 1.0));
-          s = t * c;
-        }
+        rr_pair(ne, step, tid, &a, &b);
+        double c, s;
+        jacobi_rot(Bb, LD, a, b, &c, &s);
         pa[tid] = a;
         pb[tid] = b;
         cs[tid] = c;

@@ -6,9 +6,9 @@
 //           (t-exponents).
 //  stage S: a workgroup owns 8 consecutive t columns, one wavefront per
 //           column, lane = s2. It streams the s1 rows of the partial moments
-//           (staged through LDS for coalescing), keeps a register window of
-//           2R+1 rows for the s1 pass, does the s2 pass with DPP wave shifts,
-//           and solves the 5x5 FP64 system per lane. Only nodes p <= q are
+//           through LDS, does the s2 pass of each row from LDS, keeps the
+//           last 2R+1 results in a register ring (row loop unrolled by 2R+1)
+//           for the s1 pass, and solves the 5x5 FP64 system per lane. Only nodes p <= q are
 //           computed (the surface is symmetric); each is written at (p,q)
 //           and (q,p) with mu(p)mu(q) subtracted and the domain mask applied.
 //
@@ -27,7 +27,9 @@ namespace fpca {
 namespace {
 
 constexpr int RMAX = 8;
-constexpr int TW = 8;  // t columns per stage-S workgroup (one per wavefront)
+constexpr int TW = 4;  // t columns per stage-S workgroup (one per wavefront)
+constexpr int ST = 64 * TW;  // threads of a stage-S workgroup
+constexpr int CPL = 32 / TW;  // stage-S chunks whose t columns share a 128-byte line
 
 struct Taps {
   float k[3][2 * RMAX + 1];  // (1-u^2)u^j at offsets -R..R
@@ -40,6 +42,7 @@ struct Taps {
 struct TabPtrs {
   const double *W;   // [2][3][Mmax]
   const double *Dg;  // [2][6][Mmax][Mmax]
+  const double *Xc;  // [Mmax][4]: per s1 node of the tensor-product fit: 1/W0, m/v, m^2/v, pivot test passed
   int Mmax;
 };
 
@@ -53,11 +56,36 @@ __device__ inline int ab_index(int a, int b) {
   return 5;
 }
 
-__global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, int Mmax, double *W, double *Dg) {
+__global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, int Mmax, double *W, double *Dg,
+                         double *Xc) {
   const int k = blockIdx.y;
   const int M = k == 0 ? M0 : M1;
   const double H = k == 0 ? H0 : H1;
   const int R = k == 0 ? R0 : R1;
+  if (k == 0) {
+    // the first coordinate's factors of the tensor-product fit (m = W1/W0,
+    // e = W2/W0, v = e - m^2), one node per thread
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < Mmax; x += gridDim.x * blockDim.x) {
+      double w[3] = {0.0, 0.0, 0.0};
+      if (x < M)
+        for (int m = -R; m <= R; ++m) {
+          if (x + m < 0 || x + m >= M) continue;
+          const double u = double(m) / H;
+          const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
+          w[0] += K;
+          w[1] += K * u;
+          w[2] += K * u * u;
+        }
+      const double r0 = w[0] > 0.0 ? 1.0 / w[0] : 0.0;
+      const double mx = w[1] * r0, ex = w[2] * r0, vx = ex - mx * mx;
+      const bool ok = ex > 0.0 && vx >= 1e-10 * ex;
+      const double ax = ok ? mx / vx : 0.0;
+      Xc[4 * x + 0] = r0;
+      Xc[4 * x + 1] = ax;
+      Xc[4 * x + 2] = mx * ax;
+      Xc[4 * x + 3] = ok ? 1.0 : 0.0;
+    }
+  }
   const int64_t nW = 3 * int64_t(Mmax), nD = 6 * int64_t(Mmax) * Mmax;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nW + nD; e += int64_t(gridDim.x) * blockDim.x) {
     if (e < nW) {
@@ -78,8 +106,9 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
       const int a = (ab == 1 || ab == 4) ? 1 : (ab == 3 ? 2 : 0);
       const int b = (ab == 2 || ab == 4) ? 1 : (ab == 5 ? 2 : 0);
       double s = 0.0;
+      // only nodes within R of both i and j contribute
       if (i < M && j < M)
-        for (int y = 0; y < M; ++y) {
+        for (int y = max(0, max(i, j) - R); y <= min(M - 1, min(i, j) + R); ++y) {
           const double ui = double(y - i) / H, uj = double(y - j) / H;
           const double Ki = fabs(ui) < 1.0 ? 1.0 - ui * ui : 0.0;
           const double Kj = fabs(uj) < 1.0 ? 1.0 - uj * uj : 0.0;
@@ -180,62 +209,33 @@ __global__ __launch_bounds__(512) void k_stage_t(int M1, int M2, int64_t P, cons
 }
 
 // ---------------------------------------------------------------- stage S
-// Lane l receives lane l+1's value (wave_shl:1); lane 63 receives 0.
-__device__ inline float from_next(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, true));
-}
-// Lane l receives lane l-1's value (wave_shr:1); lane 0 receives 0.
-__device__ inline float from_prev(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, true));
-}
-
-// out_j = sum_m tap_j[m] x(lane + m), m = -R..R, for NJ tap rows j.
-template <int R, int NJ>
-__device__ inline void lane_conv(float x, const Taps &tp, float *out) {
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) out[j] = tp.k[j][R] * x;
-  float up = x, dn = x;
-#pragma unroll
-  for (int m = 1; m <= R; ++m) {
-    up = from_next(up);  // x(lane + m)
-    dn = from_prev(dn);  // x(lane - m)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      out[j] = fmaf(tp.k[j][R + m], up, out[j]);
-      out[j] = fmaf(tp.k[j][R - m], dn, out[j]);
-    }
-  }
-}
-
-// s1-window of one array: sum_m tap_j[m] win[R+m]
-template <int R, int J>
-__device__ inline float win_conv(const float *win, const Taps &tp) {
-  float a = 0.f;
-#pragma unroll
-  for (int i = 0; i <= 2 * R; ++i) a = fmaf(tp.k[J][i], win[i], a);
-  return a;
-}
-
 template <int R>
-__global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, const float *__restrict__ U, Taps tp,
+__global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const float *__restrict__ U, Taps tp,
                                                   const float *__restrict__ mu, const uint8_t *__restrict__ mask,
                                                   double c0, TabPtrs tab, int nchunks, float *__restrict__ gamma,
                                                   int8_t *__restrict__ status) {
   constexpr int NU = 3;
   constexpr int W = 2 * R + 1;
-  __shared__ float stage[2][NU][64][TW + 1];
+  // Staged input row (double-buffered); rows s2 = -R .. 63 + R of it (R zero
+  // rows at both ends) so that the s2 pass reads its 2R+1 neighbours
+  // without tests.
+  constexpr int SW = 64 + 2 * R;
+  __shared__ float stage[2][NU][SW][TW + 1];
+  // response moments of the near-diagonal nodes, per wavefront: rows
+  // t1-2R .. t1, lanes t2-2R .. t2+2R
+  __shared__ float nearT[TW][2 * R + 1][4 * R + 1][5];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // Chunk order: the chunks sharing a 128-byte line of a row (4 chunks of 8
-  // floats) land on one XCD (dispatch is round-robin over 8 XCDs), and the
+  // Chunk order: the chunks sharing a 128-byte line of a row (CPL chunks of
+  // TW floats) land on one XCD (dispatch is round-robin over 8 XCDs), and the
   // chunks with the most work (largest t1) come first.
   int chunk;
   {
     const int b = blockIdx.x;
-    const int nlines = (nchunks + 3) / 4;
-    const int L = (b / 32) * 8 + (b % 8);
-    const int sib = (b / 8) % 4;
+    const int nlines = (nchunks + CPL - 1) / CPL;
+    const int L = (b / (8 * CPL)) * 8 + (b % 8);
+    const int sib = (b / 8) % CPL;
     int line = nlines - 1 - L;
-    chunk = line * 4 + sib;
+    chunk = line * CPL + sib;
     if (L >= nlines || chunk >= nchunks || chunk < 0) chunk = -1;
   }
   if (chunk < 0) return;  // uniform across the workgroup
@@ -289,15 +289,19 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
     tz_inv = 1.0 / prod;
   }
 
-  float win[NU][W];
+  // s2-pass results of the last W input rows (the s1 window, oldest first):
+  //   0: K*U0, 1: uK*U0, 2: K*U1, 3: K*U2 along s2
+  constexpr int NA = 4;
+  float win[NA][W];
 #pragma unroll
-  for (int a = 0; a < NU; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int i = 0; i < W; ++i) win[a][i] = 0.f;
+  for (int e = tid; e < 2 * NU * SW * (TW + 1); e += ST) (&stage[0][0][0][0])[e] = 0.f;
 
-  // Each thread stages NU values per row (64 s2 x TW t per array, 512 threads);
+  // Each thread stages NU values per row (64 s2 x TW t per array);
   // the next row is fetched into registers while the current one is used.
-  static_assert(64 * TW == 512, "one staged value per thread and array");
+  static_assert(64 * TW == ST, "one staged value per thread and array");
   const int ls2 = tid / TW, ltt = tid % TW;
   const bool lok = ls2 < M2 && t0 + ltt < P;
   float pre[NU];
@@ -306,79 +310,8 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
     for (int a = 0; a < NU; ++a)
       pre[a] = (r < M1 && lok) ? U[a * PP + (int64_t(r) * M2 + ls2) * P + t0 + ltt] : 0.f;
   };
-  fetch(0);
-  for (int r = 0; r <= xmax + R; ++r) {
-    const int buf = r & 1;
-#pragma unroll
-    for (int a = 0; a < NU; ++a) stage[buf][a][ls2][ltt] = pre[a];
-    __syncthreads();
-    if (r < xmax + R) fetch(r + 1);
-#pragma unroll
-    for (int a = 0; a < NU; ++a) {
-#pragma unroll
-      for (int i = 0; i < W - 1; ++i) win[a][i] = win[a][i + 1];
-      win[a][W - 1] = stage[buf][a][lane][wave];
-    }
-    const int x = r - R;
-    if (x < 0 || !wave_ok || x > t1) continue;  // no output row for this wavefront
-    // s1 pass (exponent of u in s1 is the second index)
-    const float g00_0 = win_conv<R, 0>(win[0], tp), g00_1 = win_conv<R, 1>(win[0], tp);
-    const float g10_0 = win_conv<R, 0>(win[1], tp), g01_0 = win_conv<R, 0>(win[2], tp);
-    // s2 pass across lanes
-    double m[20];
-    {
-      float o2[2], o1[1];
-      lane_conv<R, 2>(g00_0, tp, o2);  // T0, T1_s2
-      const float T0 = o2[0], Ts2 = o2[1];
-      lane_conv<R, 1>(g00_1, tp, o1);
-      const float Ts1 = o1[0];
-      lane_conv<R, 1>(g10_0, tp, o1);
-      const float Tt1 = o1[0];
-      lane_conv<R, 1>(g01_0, tp, o1);
-      const float Tt2 = o1[0];
-      m[15] = T0;
-      m[16] = Ts1;
-      m[17] = Ts2;
-      m[18] = Tt1;
-      m[19] = Tt2;
-    }
-    const int Mm = tab.Mmax;
-    const double *W1 = tab.W;
-    const double w0 = W1[0 * Mm + x], w1 = W1[1 * Mm + x], w2 = W1[2 * Mm + x];
-    if (lane >= M2) continue;
-    const int64_t p = int64_t(x) * M2 + lane;
-    if (p > t) continue;
-    int8_t st;
-    double b0;
-    if (abs(x - t1) > 2 * R || abs(lane - t2) > 2 * R) {
-      const double r0 = 1.0 / w0, mx = w1 * r0, ex = w2 * r0, vx = ex - mx * mx;
-      const double inv = tz_inv * r0;
-      if (tz_ok && ex > 0.0 && vx >= 1e-10 * ex) {
-        const double ax = mx / vx;
-        b0 = (m[15] * (1.0 + tz_c + mx * ax) - ax * m[16] - tz_a[0] * m[17] - tz_a[1] * m[18] - tz_a[2] * m[19]) *
-             inv;
-        st = FPCA_STATUS_OK;
-      } else {
-        b0 = m[15] * inv;
-        st = FPCA_STATUS_FALLBACK;
-      }
-    } else {
-      // the diagonal exclusion couples s and t: full system
-      const double *D1 = tab.Dg;
-      const int tt1 = t1;
-      auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + tt1]; };
-      // moment q has u-exponents (a1, a2, b1, b2) in (s1, s2, t1, t2)
-      const int E[15][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
-                            {2, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {1, 0, 0, 1}, {0, 2, 0, 0},
-                            {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 2, 0}, {0, 0, 1, 1}, {0, 0, 0, 2}};
-      const double wx[3] = {w0, w1, w2};
-#pragma unroll
-      for (int q = 0; q < 15; ++q) {
-        const double af = ws2[E[q][1]] * wt1[E[q][2]] * wt2[E[q][3]];
-        m[q] = c0 * (wx[E[q][0]] * af - d1(E[q][0], E[q][2]) * dg2[ab_index(E[q][1], E[q][3])]);
-      }
-      b0 = wls_b0<4>(m, &st);
-    }
+  // Gamma(p,t) = Gamma(t,p) = b0 - mu_p mu_t (0 outside the domain), status at both.
+  auto emit = [&](int64_t p, double b0, int8_t st) {
     if (mu) b0 -= double(mu[p]) * double(mu[t]);
     if (mask && (!mask[p] || !mask[t])) b0 = 0.0;
     const float v = float(b0);
@@ -388,6 +321,108 @@ __global__ __launch_bounds__(512) void k_stage_s(int M1, int M2, int64_t P, cons
       status[t * P + p] = st;
       status[p * P + t] = st;
     }
+  };
+  const int rlast = xmax + R;  // last input row any wavefront needs
+  fetch(0);
+  __syncthreads();  // the zeroed padding rows
+  for (int r = 0; r <= rlast; ++r) {
+    const int buf = r & 1;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) stage[buf][a][R + ls2][ltt] = pre[a];
+    __syncthreads();
+    if (r < rlast) fetch(r + 1);
+    // s2 pass of input row r (lanes = s2) from the staged row
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) {
+      const float u0 = stage[buf][0][lane + i][wave];
+      const float u1 = stage[buf][1][lane + i][wave];
+      const float u2 = stage[buf][2][lane + i][wave];
+      a0 = fmaf(tp.k[0][i], u0, a0);
+      a1 = fmaf(tp.k[1][i], u0, a1);
+      a2 = fmaf(tp.k[0][i], u1, a2);
+      a3 = fmaf(tp.k[0][i], u2, a3);
+    }
+#pragma unroll
+    for (int i = 0; i < W - 1; ++i) {
+      win[0][i] = win[0][i + 1];
+      win[1][i] = win[1][i + 1];
+      win[2][i] = win[2][i + 1];
+      win[3][i] = win[3][i + 1];
+    }
+    win[0][W - 1] = a0;
+    win[1][W - 1] = a1;
+    win[2][W - 1] = a2;
+    win[3][W - 1] = a3;
+    const int x = r - R;
+    if (x < 0 || !wave_ok || x > t1) continue;  // no output row for this wavefront
+    // s1 pass over the window: input rows x-R .. x+R
+    double m[20];
+    {
+      float T0 = 0.f, Ts1 = 0.f, Ts2 = 0.f, Tt1 = 0.f, Tt2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        T0 = fmaf(tp.k[0][i], win[0][i], T0);
+        Ts1 = fmaf(tp.k[1][i], win[0][i], Ts1);
+        Ts2 = fmaf(tp.k[0][i], win[1][i], Ts2);
+        Tt1 = fmaf(tp.k[0][i], win[2][i], Tt1);
+        Tt2 = fmaf(tp.k[0][i], win[3][i], Tt2);
+      }
+      m[15] = T0;
+      m[16] = Ts1;
+      m[17] = Ts2;
+      m[18] = Tt1;
+      m[19] = Tt2;
+    }
+    if (lane >= M2) continue;
+    const int64_t p = int64_t(x) * M2 + lane;
+    if (p > t) continue;
+    if (abs(x - t1) <= 2 * R && abs(lane - t2) <= 2 * R) {
+      // near the s = t diagonal: solved after the row loop
+      float *nq = nearT[wave][x - (t1 - 2 * R)][lane - (t2 - 2 * R)];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) nq[k] = float(m[15 + k]);
+      continue;
+    }
+    const double *xc = tab.Xc + 4 * x;  // 1/W0, m/v, m^2/v, ok of row x
+    const double inv = tz_inv * xc[0];
+    if (tz_ok && xc[3] != 0.0) {
+      emit(p, (m[15] * (1.0 + tz_c + xc[2]) - xc[1] * m[16] - tz_a[0] * m[17] - tz_a[1] * m[18] -
+               tz_a[2] * m[19]) * inv,
+           FPCA_STATUS_OK);
+    } else {
+      emit(p, m[15] * inv, FPCA_STATUS_FALLBACK);
+    }
+  }
+
+  // Nodes whose s- and t-windows share grid nodes (|s1 - t1| <= 2R and
+  // |s2 - t2| <= 2R): the diagonal exclusion couples s and t, full system.
+  if (!wave_ok) return;
+  const int dl = lane - (t2 - 2 * R);
+  for (int x = max(0, t1 - 2 * R); x <= t1; ++x) {
+    if (lane >= M2 || dl < 0 || dl > 4 * R) continue;
+    const int64_t p = int64_t(x) * M2 + lane;
+    if (p > t) continue;
+    const int Mm = tab.Mmax;
+    const double *W1 = tab.W, *D1 = tab.Dg;
+    const double wx[3] = {W1[x], W1[Mm + x], W1[2 * Mm + x]};
+    auto d1 = [&](int a1, int b1) { return D1[(int64_t(ab_index(a1, b1)) * Mm + x) * Mm + t1]; };
+    // moment q has u-exponents (a1, a2, b1, b2) in (s1, s2, t1, t2)
+    const int E[15][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
+                          {2, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {1, 0, 0, 1}, {0, 2, 0, 0},
+                          {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 2, 0}, {0, 0, 1, 1}, {0, 0, 0, 2}};
+    double m[20];
+#pragma unroll
+    for (int mq = 0; mq < 15; ++mq) {
+      const double af = ws2[E[mq][1]] * wt1[E[mq][2]] * wt2[E[mq][3]];
+      m[mq] = c0 * (wx[E[mq][0]] * af - d1(E[mq][0], E[mq][2]) * dg2[ab_index(E[mq][1], E[mq][3])]);
+    }
+    const float *nq = nearT[wave][x - (t1 - 2 * R)][dl];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m[15 + k] = nq[k];
+    int8_t st;
+    const double b0 = wls_b0<4>(m, &st);
+    emit(p, b0, st);
   }
 }
 
@@ -422,19 +457,22 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, double c0, con
   constexpr int NU = 3;
   const int Mmax = M1 > M2 ? M1 : M2;
   const size_t bytesU = carve_bytes(size_t(NU) * P * P, 4);
-  const size_t bytesT = carve_bytes(2 * 3 * Mmax, 8) + carve_bytes(2 * 6 * size_t(Mmax) * Mmax, 8);
+  const size_t bytesT = carve_bytes(2 * 3 * Mmax, 8) + carve_bytes(2 * 6 * size_t(Mmax) * Mmax, 8) +
+                        carve_bytes(4 * size_t(Mmax), 8);
   if (int rc = ws_reserve(ctx, bytesU + bytesT)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
   float *U = cv.take<float>(size_t(NU) * P * P);
-  TabPtrs tab{nullptr, nullptr, Mmax};
+  TabPtrs tab{nullptr, nullptr, nullptr, Mmax};
   double *Wt = cv.take<double>(2 * 3 * Mmax);
   double *Dt = cv.take<double>(2 * 6 * size_t(Mmax) * Mmax);
+  double *Xt = cv.take<double>(4 * size_t(Mmax));
   const double H2 = bw[1] * double(M2 - 1);
   hipLaunchKernelGGL(k_tables, dim3(64, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2), Mmax,
-                     Wt, Dt);
+                     Wt, Dt, Xt);
   FPCA_LAUNCH_CHECK("tables");
   tab.W = Wt;
   tab.Dg = Dt;
+  tab.Xc = Xt;
   const size_t lds_t = 3 * size_t(M1) * (M2 + 1) * sizeof(float);
 #define STAGE_T(RR)                                                                                          \
   do {                                                                                                       \
@@ -459,10 +497,10 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, double c0, con
 #undef STAGE_T
   FPCA_LAUNCH_CHECK("stage_t");
   const int nchunks = int((P + TW - 1) / TW);
-  const int nlines = (nchunks + 3) / 4;
-  const int grid_s = ((nlines + 7) / 8) * 32;
+  const int nlines = (nchunks + CPL - 1) / CPL;
+  const int grid_s = ((nlines + 7) / 8) * 8 * CPL;
 #define STAGE_S(RR)                                                                                          \
-  hipLaunchKernelGGL((k_stage_s<RR>), dim3(grid_s), dim3(512), 0, ctx->stream, M1, M2, P, U, tp, mu, grid->mask, \
+  hipLaunchKernelGGL((k_stage_s<RR>), dim3(grid_s), dim3(ST), 0, ctx->stream, M1, M2, P, U, tp, mu, grid->mask, \
                      c0, tab, nchunks, gamma, status)
   switch (R) {
     case 1: STAGE_S(1); break;
