@@ -248,11 +248,11 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
   int xmax = int(min(int64_t(P - 1), t0 + TW - 1) / M2);
   const int64_t PP = P * P;
 
-  // static per-lane factors of the analytic weight moments: window sums
-  // W[e] of the s2, t1 and t2 coordinates and the diagonal-overlap sums
-  // Dg[ab] of the second grid coordinate at (s2, t2)
-  double ws2[3], wt1[3], wt2[3], dg2[6];
-  {
+  // Per-lane factors of the analytic weight moments: window sums W[e] of
+  // the s2, t1 and t2 coordinates and the diagonal-overlap sums Dg[ab] of
+  // the second grid coordinate at (s2, t2). Loaded where needed (before and
+  // after the row loop), so they hold no registers during it.
+  auto load_factors = [&](double *ws2, double *wt1, double *wt2, double *dg2) {
     const int Mm = tab.Mmax;
     const double *W1 = tab.W, *W2 = tab.W + 3 * Mm;
     const double *D2 = tab.Dg + 6 * int64_t(Mm) * Mm;
@@ -263,9 +263,10 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
       wt1[e] = W1[e * Mm + (t1 < 0 ? 0 : t1)];
       wt2[e] = W2[e * Mm + t2];
     }
+    if (dg2)
 #pragma unroll
-    for (int ab = 0; ab < 6; ++ab) dg2[ab] = D2[(int64_t(ab) * Mm + s2) * Mm + t2];
-  }
+      for (int ab = 0; ab < 6; ++ab) dg2[ab] = D2[(int64_t(ab) * Mm + s2) * Mm + t2];
+  };
   // Tensor-product design (windows of s and t that share no node): with
   // per-coordinate window sums W0, W1, W2, m = W1/W0, e = W2/W0, v = e - m^2,
   // the fit's centered second-moment matrix is diagonal and
@@ -275,6 +276,8 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
   double tz_c = 0.0, tz_a[3] = {0.0, 0.0, 0.0}, tz_inv = 0.0;
   bool tz_ok = true;
   {
+    double ws2[3], wt1[3], wt2[3];
+    load_factors(ws2, wt1, wt2, nullptr);
     const double *tb[3] = {ws2, wt1, wt2};
     double prod = c0;
 #pragma unroll
@@ -398,6 +401,8 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
   // Nodes whose s- and t-windows share grid nodes (|s1 - t1| <= 2R and
   // |s2 - t2| <= 2R): the diagonal exclusion couples s and t, full system.
   if (!wave_ok) return;
+  double ws2[3], wt1[3], wt2[3], dg2[6];
+  load_factors(ws2, wt1, wt2, dg2);
   const int dl = lane - (t2 - 2 * R);
   for (int x = max(0, t1 - 2 * R); x <= t1; ++x) {
     if (lane >= M2 || dl < 0 || dl > 4 * R) continue;
