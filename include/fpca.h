@@ -186,6 +186,9 @@ int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const 
  *   Omega_g = P x r standard normal test matrix, r = k + oversample;
  *   Q = orth(A Omega_g); power_iters times: Q = orth(A Q), Q = orth(A Q);
  *   B = Q^T A Q; B = U diag(theta) U^T; psi = Q U.
+ * orth is CholeskyQR in FP64 (one pass between products, two passes for the
+ * Rayleigh-Ritz basis); columns whose Cholesky pivot falls below 1e-12 of
+ * their squared norm are dropped (set to zero) and left out of B.
  * The eigenvalues are the top k theta in descending order; eigenfunctions are
  * rescaled as phi = psi / sqrt(w) so that sum_p w_p phi_p^2 = 1, with the sign
  * chosen so that sum_p w_p phi_p > 0 (if that sum is below 1e-8 sum_p w_p |phi_p|,

@@ -4,11 +4,11 @@
 //
 //   test matrix  : counter-based normals (splitmix64 + Box-Muller), P x r
 //   products     : Gamma X on MFMA (FP32) with split K, FP64 reduction
-//   orthonormal  : CholeskyQR2 in FP64 (columns that become numerically
+//   orthonormal  : CholeskyQR in FP64 between products, CholeskyQR2 before
+//                  the Rayleigh-Ritz step (columns that become numerically
 //                  dependent are dropped: their basis vector is set to 0);
 //                  row kernels on 16-row chunks, a fixed-order sum of the
-//                  partial Gram matrices, a one-wavefront factorization
-
+//                  partial Gram matrices, a one-workgroup factorization
 //   Rayleigh-Ritz: B = Q^T A Q in FP64, eigenpairs by a one-workgroup
 //                  parallel-ordered cyclic Jacobi method in FP64
 //   finalize     : psi = Q U, phi = psi / sqrt(w), sign rule, FVE.
@@ -757,6 +757,16 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
     return FPCA_OK;
   };
   // CholeskyQR2 of Y (whose partial Gram is in gpart): Y -> Z -> Q, X.
+  // CholeskyQR of Y (one pass; the basis of an intermediate power step only
+  // has to span the subspace, its loss of orthogonality is about cond(Y)^2 u
+  // and the next product and QR remove it): Y -> Q, X.
+  auto cholqr1 = [&]() -> int {
+    if (int rc = factor()) return rc;
+    hipLaunchKernelGGL((k_rows_apply<T, false, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, Y, Rinv,
+                       sw, Q, X, (double *)nullptr);
+    FPCA_LAUNCH_CHECK("rows_apply");
+    return FPCA_OK;
+  };
   auto cholqr2 = [&]() -> int {
     if (int rc = factor()) return rc;
     hipLaunchKernelGGL((k_rows_apply<T, true, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, Y, Rinv, sw,
@@ -769,11 +779,12 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
     return FPCA_OK;
   };
 
-  if (int rc = product(Y, 1)) return rc;
-  if (int rc = cholqr2()) return rc;
-  for (int it = 0; it < 2 * power_iters; ++it) {
+  // orthonormalizations: single CholeskyQR between products, CholeskyQR2 for
+  // the basis of the Rayleigh-Ritz step
+  const int nprod = 1 + 2 * power_iters;
+  for (int it = 0; it < nprod; ++it) {
     if (int rc = product(Y, 1)) return rc;
-    if (int rc = cholqr2()) return rc;
+    if (int rc = (it + 1 < nprod) ? cholqr1() : cholqr2()) return rc;
   }
   if (int rc = product(Z, 2)) return rc;  // Z = A Q and the partials of Q^T Z
   hipLaunchKernelGGL(k_sum_gram<RP>, dim3(unsigned((RP * RP + 256 / SG - 1) / (256 / SG))), dim3(256), 0, ctx->stream,
