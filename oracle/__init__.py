@@ -205,6 +205,20 @@ def bin_common_grid(Y):
     return c, s, C, G
 
 
+def bin_common_grid_entries(Y, p, q):
+    """Entries G[p_i, q_i] of the common-grid pair sums (same definition as
+    bin_common_grid: sum over curves of Y[:, p] Y[:, q] / (P(P-1)), zero on the
+    diagonal), one dot product per entry, for sizes where the full product is
+    too large."""
+    Y = np.asarray(Y, np.float64)
+    P = Y.shape[1]
+    p = np.asarray(p, np.int64)
+    q = np.asarray(q, np.int64)
+    out = np.einsum("ij,ij->j", Y[:, p], Y[:, q]) / (P * (P - 1))
+    out[p == q] = 0.0
+    return out
+
+
 # ----------------------------------------------------------------- smoothing
 def num_moments(D: int) -> int:
     return 1 + D + D * (D + 1) // 2 + 1 + D

@@ -1,7 +1,10 @@
 // Symmetric Gram products C = alpha * A^T A for the covariance binning
 // (the Gram form of the pair sums of eq. 2.4): A is K x N row-major (one row
 // per curve), C is N x N. Only tiles on or above the diagonal are computed;
-// each is also written transposed below the diagonal.
+// each is also written transposed below the diagonal, and a diagonal tile
+// keeps its upper triangle and mirrors it, so C is exactly symmetric.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace fpca {
@@ -17,14 +20,11 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 constexpr int XCDS = 8;  // workgroups are dispatched round-robin over the XCDs
 constexpr int BAND = 8;  // tile columns per band of the schedule
 
-// Tile (bi, bj), bi <= bj, of workgroup `id`; false for a padding workgroup.
-// Workgroup id runs on XCD id % 8, and each XCD takes a contiguous run of
-// `per` tiles in band order (bands of 8 tile columns; within a band, rows top
-// to bottom with the band's columns of a row together, then the band's
-// diagonal triangle), so the tiles sharing one L2 cover a compact block of
-// rows and columns and reuse each other's operand slabs.
-__device__ inline bool tile_of(int id, int nb, int per, int *bi, int *bj) {
-  int t = (id % XCDS) * per + id / XCDS;
+// Tile number t (0 <= t < nb(nb+1)/2) in band order -> (bi, bj), bi <= bj:
+// bands of 8 tile columns; within a band, rows top to bottom with the band's
+// columns of a row together, then the band's diagonal triangle. A run of
+// consecutive tiles covers a compact block of rows and columns.
+__device__ inline bool band_tile(int t, int nb, int *bi, int *bj) {
   for (int J0 = 0; J0 < nb; J0 += BAND) {
     const int w = min(BAND, nb - J0);
     const int full = J0 * w;  // rows 0 .. J0-1, w columns each
@@ -47,6 +47,13 @@ __device__ inline bool tile_of(int id, int nb, int per, int *bi, int *bj) {
     t -= cnt;
   }
   return false;
+}
+
+// Tile of workgroup `id` (false for a padding workgroup): workgroup id runs on
+// XCD id % 8, and each XCD takes a contiguous run of `per` tiles in band
+// order, so the tiles sharing one L2 reuse each other's operand slabs.
+__device__ inline bool tile_of(int id, int nb, int per, int *bi, int *bj) {
+  return band_tile((id % XCDS) * per + id / XCDS, nb, bi, bj);
 }
 
 // bf16 split of an FP32 value: hi = round-to-nearest-even bf16(x), lo = bf16(x - hi).
@@ -147,10 +154,13 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
         const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
         const int64_t c = n0 + wn * 64 + j * 16 + (lane & 15);
         if (r < N && c < N) {
-          float val = alpha * acc[i][j][v];
-          if (zero_diag && r == c) val = 0.f;
-          C[r * ldc + c] = val;
-          if (!diag_tile) C[c * ldc + r] = val;
+          // upper triangle and its mirror: C is exactly symmetric
+          if (!diag_tile || r <= c) {
+            float val = alpha * acc[i][j][v];
+            if (zero_diag && r == c) val = 0.f;
+            C[r * ldc + c] = val;
+            if (r != c) C[c * ldc + r] = val;
+          }
         }
       }
 }
@@ -182,116 +192,263 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, in
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// C = alpha * A^T A from the split operands, 128x128 tile per workgroup (tiles on
-// or above the diagonal, mirrored), 4 wavefronts of 64x64, K step 32, double-
+// Work split of the persistent SYRK (all tile numbers in band order, S K
+// steps per tile, G workgroups, tiles = F G + W with 0 <= W < G):
+//  - "whole" tiles 0 .. D-1, D = tiles - 2W (or all tiles when W = 0): wave f
+//    gives workgroup w the tile f G + slot(w), slot(w) = (w % 8) (G / 8) + w / 8,
+//    so the tiles of one XCD are a contiguous run; every whole tile starts at
+//    K step 0 on all workgroups together, which keeps the operand slabs that
+//    neighbouring tiles share in the XCD's L2;
+//  - the last 2W tiles ("split" tiles q = 0 .. 2W-1, R = 2 W S iterations)
+//    are cut into contiguous chunks: the W workgroups without a tile in the
+//    last wave take cap_hi iterations each, the others cap_lo, in that order
+//    (rank u). The piece of chunk u in split tile q leaves its accumulators in
+//    partial slot u + q: along the iterations every chunk or tile boundary
+//    raises u or q, so the slots of the pieces are distinct and below G + 2W.
+struct SkPlan {
+  int G, S, F, W, D;     // D: number of whole tiles
+  int cap_hi, cap_lo;    // chunk sizes of the split tiles
+  int64_t R;             // iterations of the split tiles
+};
+
+__device__ inline int sk_slot(const SkPlan &pl, int w) { return (w % XCDS) * (pl.G / XCDS) + w / XCDS; }
+// rank of workgroup w in the order of the split-tile chunks
+__device__ inline int sk_rank(const SkPlan &pl, int w) {
+  const int sl = sk_slot(pl, w);
+  return sl >= pl.G - pl.W ? sl - (pl.G - pl.W) : pl.W + sl;
+}
+__device__ inline int64_t sk_begin(const SkPlan &pl, int u) {
+  const int64_t b = u < pl.W ? int64_t(u) * pl.cap_hi : int64_t(pl.W) * pl.cap_hi + int64_t(u - pl.W) * pl.cap_lo;
+  return min(b, pl.R);
+}
+__device__ inline int64_t sk_end(const SkPlan &pl, int u) {
+  return min(sk_begin(pl, u) + (u < pl.W ? pl.cap_hi : pl.cap_lo), pl.R);
+}
+
+// C = alpha * A^T A from the split operands; tiles of 128x128 on or above the
+// diagonal (mirrored), 4 wavefronts of 64x64, K steps of 32 through double-
 // buffered LDS. Per 16x16 block and K step: lo*hi + hi*lo + hi*hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the lo*lo term, below
-// 2^-16 of the product, is dropped).
-__global__ __launch_bounds__(256) void k_syrk_bf16x3(const unsigned short *__restrict__ Th,
-                                                      const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
-                                                      float *__restrict__ C, int64_t ldc, float alpha, int zero_diag,
-                                                      int nb, int per) {
+// 2^-16 of the product, is dropped). Whole tiles are written to C; a piece of
+// a split tile leaves its accumulators in its partial slot for k_syrk_fixup.
+__global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__restrict__ Th,
+                                                         const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
+                                                         float *__restrict__ C, int64_t ldc, float alpha,
+                                                         int zero_diag, int nb, SkPlan pl,
+                                                         float *__restrict__ part) {
   constexpr int BK = 32;
   constexpr int LR = BK + 8;  // padded LDS row in bf16 elements (80 bytes)
   __shared__ __attribute__((aligned(16))) unsigned short S[2][4][TB][LR];  // [buf][Ah Al Bh Bl][row][k]
-  int bi, bj;
-  if (!tile_of(blockIdx.x, nb, per, &bi, &bj)) return;  // uniform per workgroup
-  const bool diag_tile = (bi == bj);
+  const int w = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = int64_t(bi) * TB, n0 = int64_t(bj) * TB;
-  const int narr = diag_tile ? 2 : 4;
-  float4_t acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-  // staging: 128 rows x 4 chunks of 16 bytes per array; 2 chunks per thread
-  u16x8 st[4][2];
-  auto load = [&](int64_t kb) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (a >= narr) break;
-      const unsigned short *src = (a & 1) ? Tl : Th;
-      const int64_t r0 = (a < 2) ? m0 : n0;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = tid + 256 * h;
-        const int row = c >> 2, part = c & 3;
-        const int64_t gr = r0 + row;
-        if (gr < N)
-          st[a][h] = *reinterpret_cast<const u16x8 *>(src + gr * Kp + kb + part * 8);
-        else
-          st[a][h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (a >= narr) break;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = tid + 256 * h;
-        *reinterpret_cast<u16x8 *>(&S[buf][a][c >> 2][(c & 3) * 8]) = st[a][h];
-      }
-    }
-  };
-  int buf = 0;
-  load(0);
-  store(0);
-  __syncthreads();
-  const int bh = diag_tile ? 0 : 2, bl = diag_tile ? 1 : 3;
   const int kq = (lane >> 4) * 8;
-  for (int64_t kb = 0; kb < Kp; kb += BK) {
-    const bool more = kb + BK < Kp;
-    if (more) load(kb + BK);
-    bf16x8 ah[4], al[4], bhv[4], blv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wm * 64 + i * 16 + (lane & 15);
-      ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][0][r][kq]));
-      al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][1][r][kq]));
-      const int c = wn * 64 + i * 16 + (lane & 15);
-      bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bh][c][kq]));
-      blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bl][c][kq]));
+  const int u = sk_rank(pl, w);
+  const int64_t j0 = sk_begin(pl, u), j1 = sk_end(pl, u);
+  const int nwhole = pl.F;  // waves of whole tiles
+  // segment g: whole tile of wave g (g < nwhole), then chunks of split tiles
+  int64_t j = j0;
+#pragma unroll 1
+  for (int g = 0;; ++g) {
+    int t, k0, k1, slot = -1;  // slot >= 0: a piece of a split tile
+    if (g < nwhole) {
+      t = g * pl.G + sk_slot(pl, w);
+      if (t >= pl.D) continue;
+      k0 = 0;
+      k1 = pl.S;
+    } else {
+      if (j >= j1) break;
+      const int q = int(j / pl.S);
+      t = pl.D + q;
+      k0 = int(j % pl.S);
+      k1 = int(min(int64_t(pl.S), k0 + (j1 - j)));
+      slot = u + q;
+      j += k1 - k0;
     }
-    // the three products of a block are 16 MFMAs apart (independent
-    // accumulators in between), so no MFMA waits on its predecessor
+    int bi, bj;
+    band_tile(t, nb, &bi, &bj);
+    const bool diag_tile = (bi == bj);
+    const int64_t m0 = int64_t(bi) * TB, n0 = int64_t(bj) * TB;
+    const int narr = diag_tile ? 2 : 4;
+    float4_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
+      for (int jj = 0; jj < 4; ++jj) acc[i][jj] = float4_t{0.f, 0.f, 0.f, 0.f};
+    // staging: 128 rows x 4 chunks of 16 bytes per array; 2 chunks per thread
+    u16x8 st[4][2];
+    auto load = [&](int64_t kb) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int a = 0; a < 4; ++a) {
+        if (a >= narr) break;
+        const unsigned short *src = (a & 1) ? Tl : Th;
+        const int64_t r0 = (a < 2) ? m0 : n0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[j], acc[i][j], 0, 0, 0);
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
-        const int64_t c = n0 + wn * 64 + j * 16 + (lane & 15);
-        if (r < N && c < N) {
-          float val = alpha * acc[i][j][v];
-          if (zero_diag && r == c) val = 0.f;
-          C[r * ldc + c] = val;
-          if (!diag_tile) C[c * ldc + r] = val;
+        for (int h = 0; h < 2; ++h) {
+          const int c = tid + 256 * h;
+          const int row = c >> 2, pt = c & 3;
+          const int64_t gr = r0 + row;
+          if (gr < N)
+            st[a][h] = *reinterpret_cast<const u16x8 *>(src + gr * Kp + kb + pt * 8);
+          else
+            st[a][h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
       }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a >= narr) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c = tid + 256 * h;
+          *reinterpret_cast<u16x8 *>(&S[buf][a][c >> 2][(c & 3) * 8]) = st[a][h];
+        }
+      }
+    };
+    const int bh = diag_tile ? 0 : 2, bl = diag_tile ? 1 : 3;
+    const int64_t kb0 = int64_t(k0) * BK, kb1 = int64_t(k1) * BK;
+    int buf = 0;
+    load(kb0);
+    store(0);
+    __syncthreads();
+    for (int64_t kb = kb0; kb < kb1; kb += BK) {
+      const bool more = kb + BK < kb1;
+      if (more) load(kb + BK);
+      bf16x8 ah[4], al[4], bhv[4], blv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm * 64 + i * 16 + (lane & 15);
+        ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][0][r][kq]));
+        al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][1][r][kq]));
+        const int c = wn * 64 + i * 16 + (lane & 15);
+        bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bh][c][kq]));
+        blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bl][c][kq]));
+      }
+      // the three products of a block are 16 MFMAs apart (independent
+      // accumulators in between), so no MFMA waits on its predecessor
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bhv[jj], acc[i][jj], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blv[jj], acc[i][jj], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[jj], acc[i][jj], 0, 0, 0);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // D layout of a 16x16 MFMA block: lane l, element e -> row 4*(l/16)+e, column l%16
+    if (slot < 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
+            const int64_t c = n0 + wn * 64 + jj * 16 + (lane & 15);
+            if (r < N && c < N && (!diag_tile || r <= c)) {  // upper triangle and its mirror
+              float val = alpha * acc[i][jj][e];
+              if (zero_diag && r == c) val = 0.f;
+              C[r * ldc + c] = val;
+              if (r != c) C[c * ldc + r] = val;
+            }
+          }
+    } else {
+      float *dst = part + int64_t(slot) * (TB * TB) + (wm * 64 + 4 * (lane >> 4)) * TB + wn * 64 +
+                   (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float *row = dst + (i * 16 + e) * TB;
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) row[jj * 16] = acc[i][jj][e];
+        }
+    }
+  }
 }
 
-// Plain VALU Gram product for FP64 values and exact integer counts:
+// Split tiles of k_syrk_bf16x3: workgroup (q, slab) adds, in chunk order, the
+// pieces of split tile q for 8 rows of the tile (one float4 per thread, the
+// pieces' loads issued together) and writes them, and their mirror through an
+// LDS transpose, to C.
+constexpr int FX_ROWS = 8;
+__global__ __launch_bounds__(256) void k_syrk_fixup(const float *__restrict__ part, SkPlan pl, int nb, int64_t N,
+                                                     float *__restrict__ C, int64_t ldc, float alpha, int zero_diag) {
+  __shared__ float T[FX_ROWS][TB + 1];
+  __shared__ const float *src[64];  // the host keeps the pieces of a tile below 64
+  __shared__ int nsrc;
+  const int q = blockIdx.x / (TB / FX_ROWS), rb = (blockIdx.x % (TB / FX_ROWS)) * FX_ROWS;
+  int bi, bj;
+  band_tile(pl.D + q, nb, &bi, &bj);
+  const int64_t m0 = int64_t(bi) * TB, n0 = int64_t(bj) * TB;
+  const int tid = threadIdx.x;
+  if (tid < 64) {  // wave 0: chunks u0 .. u0 + 63 that overlap iterations [q S, (q+1) S)
+    const int64_t a = int64_t(q) * pl.S, b = a + pl.S;
+    const int64_t hi_end = int64_t(pl.W) * pl.cap_hi;  // first chunk ending after a
+    const int u0 = a < hi_end ? int(a / pl.cap_hi) : pl.W + int((a - hi_end) / pl.cap_lo);
+    const int u = u0 + tid;
+    bool ov = false;
+    if (u < pl.G) {
+      const int64_t j0 = sk_begin(pl, u), j1 = sk_end(pl, u);
+      ov = j0 < b && j1 > a;
+    }
+    if (ov) src[tid] = part + int64_t(u + q) * (TB * TB) + int64_t(rb) * TB;
+    const uint64_t m = __ballot(ov);  // the overlapping chunks are consecutive from u0
+    if (tid == 0) nsrc = __popcll(m);
+  }
+  __syncthreads();
+  const int ns = nsrc;
+  const int rr = tid >> 5, c4 = (tid & 31) * 4;
+  const int off = rr * TB + c4;
+  float4_t sum = float4_t{0.f, 0.f, 0.f, 0.f};
+  int k = 0;
+  for (; k + 4 <= ns; k += 4) {
+    const float4_t v0 = *reinterpret_cast<const float4_t *>(src[k] + off);
+    const float4_t v1 = *reinterpret_cast<const float4_t *>(src[k + 1] + off);
+    const float4_t v2 = *reinterpret_cast<const float4_t *>(src[k + 2] + off);
+    const float4_t v3 = *reinterpret_cast<const float4_t *>(src[k + 3] + off);
+    sum += v0;
+    sum += v1;
+    sum += v2;
+    sum += v3;
+  }
+  for (; k < ns; ++k) sum += *reinterpret_cast<const float4_t *>(src[k] + off);
+  const int64_t r = m0 + rb + rr;
+  const bool diag_tile = (bi == bj);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t cc = n0 + c4 + i;
+    float val = alpha * sum[i];
+    if (zero_diag && r == cc) val = 0.f;
+    T[rr][c4 + i] = val;
+    if (r < N && cc < N && (!diag_tile || r <= cc)) {  // a diagonal tile: upper triangle and its mirror
+      C[r * ldc + cc] = val;
+      if (diag_tile && r != cc) C[cc * ldc + r] = val;
+    }
+  }
+  __syncthreads();
+  if (!diag_tile) {  // mirror: row n0 + c, columns m0 + rb .. m0 + rb + 7
+    const int c = tid >> 1, r4 = (tid & 1) * 4;
+    const int64_t mr = n0 + c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t cc = m0 + rb + r4 + i;
+      if (mr < N && cc < N) C[mr * ldc + cc] = T[r4 + i][c];
+    }
+  }
+}
+
 // 64x64 output tile, 256 threads with 4x4 outputs each, all tiles computed.
 template <typename Tin, typename Tacc, typename Tout>
 __global__ __launch_bounds__(256) void k_gram_valu(const Tin *__restrict__ A, int64_t K, int64_t N,
@@ -345,17 +502,51 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
   bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   if (prec == FPCA_PREC_BF16X3) {
     const int64_t Kp = ((K + 31) / 32) * 32;
+    const int64_t nsteps = Kp / 32;
+    // persistent workgroups: two per CU, a multiple of the XCD count
+    int G = 2 * ctx->num_cus;
+    G = (G / XCDS) * XCDS;
+    if (G < XCDS) G = XCDS;
+    SkPlan pl{};
+    pl.G = G;
+    pl.S = int(nsteps);
+    pl.F = tiles / G;
+    pl.W = tiles % G;
+    if (pl.F == 0) {  // a single partial wave: whole tiles only
+      pl.F = 1;
+      pl.W = 0;
+    }
+    pl.D = tiles - 2 * pl.W;
+    pl.R = int64_t(2) * pl.W * nsteps;
+    // chunks of the split tiles: each workgroup ends near ceil(tiles S / G)
+    // steps; at most 60 chunks per split tile
+    const int64_t c = pl.W > 0 ? std::max<int64_t>((int64_t(pl.W) * nsteps + G - 1) / G, (nsteps + 59) / 60) : 0;
+    pl.cap_lo = int(c);
+    pl.cap_hi = int(nsteps + c);
     const size_t half = carve_bytes(size_t(N) * size_t(Kp), 2);
-    if (int rc = ws2_reserve(ctx, 2 * half)) return rc;
+    const size_t pbytes = carve_bytes(size_t(G + 2 * pl.W) * TB * TB, 4);
+    if (int rc = ws2_reserve(ctx, 2 * half + pbytes)) return rc;
     unsigned short *Th = static_cast<unsigned short *>(ctx->ws2);
     unsigned short *Tl = reinterpret_cast<unsigned short *>(static_cast<char *>(ctx->ws2) + half);
-    if (Kp > 0) {
-      dim3 gs((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
-      hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
-      FPCA_LAUNCH_CHECK("split_t");
+    float *part = reinterpret_cast<float *>(static_cast<char *>(ctx->ws2) + 2 * half);
+    if (nsteps == 0) {  // K = 0: the product is zero
+      if (ldc == N) return fill_f32(ctx, C, 0.f, N * N);
+      for (int64_t r = 0; r < N; ++r)
+        if (int rc = fill_f32(ctx, C + r * ldc, 0.f, N)) return rc;
+      return FPCA_OK;
     }
-    hipLaunchKernelGGL(k_syrk_bf16x3, dim3(grid), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
-                       int(zero_diag), nb, per);
+    dim3 gs((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
+    hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
+    FPCA_LAUNCH_CHECK("split_t");
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3(unsigned(G)), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
+                       int(zero_diag), nb, pl, part);
+    FPCA_LAUNCH_CHECK("syrk_bf16x3");
+    if (pl.W > 0) {
+      hipLaunchKernelGGL(k_syrk_fixup, dim3(unsigned(2 * pl.W * (TB / FX_ROWS))), dim3(256), 0, ctx->stream, part, pl, nb, N,
+                         C, ldc,
+                         alpha, int(zero_diag));
+      FPCA_LAUNCH_CHECK("syrk_fixup");
+    }
   } else {
     if (vec)
       hipLaunchKernelGGL((k_syrk_f32<true>), dim3(grid), dim3(256), 0, ctx->stream, A, K, N, C, ldc, alpha,

@@ -163,8 +163,35 @@ def test_bin_cov_common_grid(torch, F, h, prec, tol, M):
     assert normwise_rel(host(G), rG) < tol
     assert np.array_equal(host(G), host(G2))
     assert np.all(np.diag(host(G)) == 0)
+    assert np.array_equal(host(G), host(G).T)
     assert normwise_rel(host(c), rc) < 1e-7 and normwise_rel(host(s), rs) < 1e-5
     assert normwise_rel(host(s2), rs2) < 1e-5
+
+
+@pytest.mark.parametrize("M,n", [((64, 64), 5000), ((64, 70), 3001), ((64, 96), 1000)])
+def test_bin_cov_common_grid_bf16x3_full(torch, F, h, M, n):
+    """BF16x3 Gram product at full size, where the upper-triangle tiles outnumber
+    the resident workgroups and the last tiles are split along the curves
+    (K ragged for n = 3001): sampled entries and whole rows against the oracle's
+    per-entry sums; exact symmetry and a zero diagonal over the whole matrix."""
+    _say(f"bin_cov common bf16x3 full M={M} n={n}")
+    rng = np.random.default_rng(17)
+    P = int(np.prod(M))
+    Y = rng.standard_normal((n, P)).astype(np.float32)
+    G = torch.empty(P, P, dtype=torch.float32, device="cuda:0")
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, F.FPCA_F32, F.FPCA_PREC_BF16X3, n, None, None,
+               dev(torch, Y), None, 0, None, G)
+    h.sync()
+    Gh = host(G)
+    assert np.array_equal(Gh, Gh.T)
+    assert np.all(np.diag(Gh) == 0)
+    rows = np.concatenate([rng.integers(0, P, 4), rng.integers(P - P // 8, P, 4)])
+    pr = np.repeat(rows, P)
+    qr = np.tile(np.arange(P), len(rows))
+    ps, qs = rng.integers(0, P, 4000), rng.integers(0, P, 4000)
+    p, q = np.concatenate([pr, ps]), np.concatenate([qr, qs])
+    ref = oracle.bin_common_grid_entries(Y, p, q)
+    assert normwise_rel(Gh[p, q], ref) < 1e-4
 
 
 def test_domain_error_reported(torch, F, h):
