@@ -196,8 +196,8 @@ def main():
     stream = torch.cuda.current_stream()
     gram_prec = F.FPCA_PREC_BF16X3 if args.gram_prec == "bf16x3" else F.FPCA_PREC_F32
 
-    def step(record=None):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if record is not None else None
+    def step(ev=None):
+        """One pass of the path; `ev`: five timing events (created outside the timed loop) or None."""
         if ev: ev[0].record(stream)
         F.fpca_bin(h, dd.grid_mean, F.FPCA_BIN_MEAN, dd.design, dd.dtype, F.FPCA_PREC_F32, dd.n, None, None,
                    dd.y, None, 0, bufs.c, bufs.s)
@@ -215,18 +215,17 @@ def main():
                                                      bufs.efuns)
         if ev:
             ev[4].record(stream)
-            record.append(ev)
 
     log("warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log("timed steps")
-    recs = []
+    recs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(recs)
+    for i in range(args.steps):
+        step(recs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     h.sync()

@@ -34,6 +34,9 @@ struct fpca_context {
   // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
   int *d_flags = nullptr;
   int *h_flags = nullptr;  // pinned mirror
+  // Pinned staging for small device-to-host results (eigenvalues and FVE).
+  static constexpr size_t kStageBytes = 4096;
+  double *h_stage = nullptr;
   int num_cus = 256;
 };
 

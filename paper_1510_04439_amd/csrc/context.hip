@@ -160,7 +160,10 @@ int fpca_create(fpca_handle *handle, int device) {
   ctx->device = device;
   ctx->num_cus = prop.multiProcessorCount;
   if (const char *lim = std::getenv("FPCA_DEBUG_WS_LIMIT")) ctx->ws_limit = std::strtoull(lim, nullptr, 10);
-  if (hipMalloc(&ctx->d_flags, 256) != hipSuccess || hipHostMalloc(&ctx->h_flags, 256) != hipSuccess) {
+  if (hipMalloc(&ctx->d_flags, 256) != hipSuccess || hipHostMalloc(&ctx->h_flags, 256) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&ctx->h_stage), fpca_context::kStageBytes) != hipSuccess) {
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     delete ctx;
     return set_error(FPCA_ERR_DEVICE, "flag allocation failed");
   }
@@ -183,6 +186,7 @@ int fpca_destroy(fpca_handle ctx) {
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   delete ctx;
   return FPCA_OK;
 }

@@ -294,65 +294,76 @@ __device__ inline double rcp_nr(double x) {
   return y * fma(-x, y, 2.0);
 }
 
-// G = L L^T in one workgroup, one thread per matrix entry. Column j: the
-// pivot is the current A[j][j]; if it is <= 1e-12 of the original diagonal
-// (or that is <= 0) the column is dropped (L[:, j] = 0, L[j][j] = 1),
-// otherwise every entry (r, c), j < c <= r, takes
-//   A[r][c] -= (A[r][j] / sqrt(piv)) (A[c][j] / sqrt(piv)),
-// column j itself is scaled after the loop. Then X = L^{-1} by right-looking
-// forward substitution (step k: X[k][:] = B[k][:] / L[k][k], rows below
-// updated). Rinv[j][r] = X[r][j], i.e. Rinv = R^{-1} for R = L^T, with the
+// G = L L^T and L^{-1} in one workgroup by elimination on [G | I]: step j
+// (pivot p_j = the current M[j][j]) subtracts (M[r][j] / p_j) times row j from
+// every row r > j, over columns j+1.. of the G part and 0..j of the I part.
+// Afterwards row r holds p_r on its diagonal and the unit lower triangular
+// inverse in its I part, so L^{-1}[r][c] = M[r][RP + c] / sqrt(p_r). A step
+// whose pivot is <= 1e-12 of the original diagonal entry (or that entry is
+// <= 0) eliminates nothing: its column is dropped. Steps j and j + 1 share one
+// barrier: each thread forms row j + 1 after step j, its pivot and its
+// multipliers from the values before step j (every thread the same bits);
+// row j + 1's final pivot and I part go to Dodd / Lodd, since other threads
+// still read its old values. Rinv[c][r] = L^{-1}[r][c] (R = L^T) with the
 // columns of dropped vectors zeroed; act[j] = 1 for kept columns.
 template <int RP>
 __global__ __launch_bounds__(CT) void k_chol(const double *__restrict__ G, double *__restrict__ Rinv,
                                              int *__restrict__ act) {
-  __shared__ double A[RP][RP + 1];
-  __shared__ double B[RP][RP + 1];
-  __shared__ double diag[RP], rs[RP];
+  static_assert(RP % 2 == 0, "steps go in pairs");
+  constexpr int LD = 2 * RP + 1;
+  __shared__ double M[RP * LD];
+  __shared__ double Lodd[RP / 2][RP];  // I part of rows 1, 3, 5, ...
+  __shared__ double Dodd[RP / 2];      // pivots of rows 1, 3, 5, ...
+  __shared__ double diag[RP];
   __shared__ int keep[RP];
   const int tid = threadIdx.x;
   for (int e = tid; e < RP * RP; e += CT) {
     const int r = e / RP, c = e % RP;
-    A[r][c] = G[e];
-    B[r][c] = (r == c) ? 1.0 : 0.0;
+    M[r * LD + c] = G[e];
+    M[r * LD + RP + c] = (r == c) ? 1.0 : 0.0;
   }
+  for (int e = tid; e < (RP / 2) * RP; e += CT) Lodd[e / RP][e % RP] = 0.0;  // upper triangle stays 0
   if (tid < RP) diag[tid] = G[tid * RP + tid];
   __syncthreads();
-  for (int j = 0; j < RP; ++j) {
-    const double piv = A[j][j];
-    const bool ok = diag[j] > 0.0 && piv > 1e-12 * diag[j];
-    if (ok) {
-      const double rl = rsqrt_nr(piv);
-      for (int e = tid; e < RP * RP; e += CT) {
-        const int r = e / RP, c = e % RP;
-        if (c > j && c <= r) A[r][c] -= (A[r][j] * rl) * (A[c][j] * rl);
+  for (int j = 0; j < RP; j += 2) {
+    const int j1 = j + 1;
+    const double pj = M[j * LD + j];
+    const bool okj = diag[j] > 0.0 && pj > 1e-12 * diag[j];
+    const double rpj = okj ? rcp_nr(pj) : 0.0;
+    const double mj1 = M[j1 * LD + j] * rpj;  // row j + 1's multiplier at step j
+    const double p1 = fma(-mj1, M[j * LD + j1], M[j1 * LD + j1]);
+    const bool ok1 = diag[j1] > 0.0 && p1 > 1e-12 * diag[j1];
+    const double rp1 = ok1 ? rcp_nr(p1) : 0.0;
+    // row rr = 0 is j + 1 (step j only), rows rr > 0 are j + 1 + rr (both
+    // steps); columns: G part j+1 .. RP-1 (nb of them), then I part 0 .. j+1
+    const int nb = RP - 1 - j;
+    for (int e = tid; e < (RP - 1 - j) * (RP + 1); e += CT) {
+      const int rr = e / (RP + 1), cc = e % (RP + 1);
+      const int r = j1 + rr;
+      const int col = cc < nb ? j1 + cc : RP + cc - nb;
+      const double mrj = M[r * LD + j] * rpj;
+      const double vj = M[j * LD + col];
+      const double v = fma(-mrj, vj, M[r * LD + col]);  // after step j
+      if (rr == 0) {
+        if (col == j1) Dodd[j1 / 2] = v;
+        if (col >= RP) Lodd[j1 / 2][col - RP] = v;
+      } else if (col != j1) {  // column j + 1 below the diagonal is not read again
+        const double v1 = fma(-mj1, vj, M[j1 * LD + col]);                     // row j + 1 after step j
+        const double m1 = fma(-mrj, M[j * LD + j1], M[r * LD + j1]) * rp1;  // multiplier at step j + 1
+        M[r * LD + col] = fma(-m1, v1, v);
       }
     }
     if (tid == 0) {
-      rs[j] = ok ? rsqrt_nr(piv) : 1.0;  // 1 / L[j][j]
-      keep[j] = ok ? 1 : 0;
-    }
-    __syncthreads();
-  }
-  // L: column j scaled by rs[j] (diagonal: piv * rs = sqrt(piv)); dropped columns 0, diagonal 1
-  for (int e = tid; e < RP * RP; e += CT) {
-    const int r = e / RP, c = e % RP;
-    if (c < r) A[r][c] = keep[c] ? A[r][c] * rs[c] : 0.0;
-    if (c == r) A[r][c] = keep[c] ? A[r][c] * rs[c] : 1.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < RP; ++k) {
-    const double dk = keep[k] ? rs[k] : 1.0;  // 1 / L[k][k]
-    for (int e = tid; e < RP * RP; e += CT) {
-      const int r = e / RP, j = e % RP;
-      if (r > k) B[r][j] -= A[r][k] * (B[k][j] * dk);
+      keep[j] = okj ? 1 : 0;
+      keep[j1] = ok1 ? 1 : 0;
     }
     __syncthreads();
   }
   for (int e = tid; e < RP * RP; e += CT) {
-    const int j = e / RP, r = e % RP;
-    const double dr = keep[r] ? rs[r] : 1.0;
-    Rinv[e] = keep[r] ? B[r][j] * dr : 0.0;
+    const int c = e / RP, r = e % RP;
+    const double pr = (r & 1) ? Dodd[r / 2] : M[r * LD + r];
+    const double lv = (r & 1) ? Lodd[r / 2][c] : M[r * LD + RP + c];
+    Rinv[e] = keep[r] ? lv * rsqrt_nr(pr) : 0.0;
   }
   if (tid < RP) act[tid] = keep[tid];
 }
@@ -410,26 +421,30 @@ __global__ __launch_bounds__(RT) void k_rows_apply(int64_t P, const double *__re
   rows_gram<RP>(Ys, Ys, gpart + int64_t(blockIdx.x) * RP * RP, tid);
 }
 
-constexpr int JT = 1024;  // threads of the Jacobi kernel
-
-// Rotation (c, s) that annihilates B[a][b] of the symmetric matrix in Bm
-// (row stride LD): t = tan of the smaller angle, c = cos, s = sin.
-__device__ inline void jacobi_rot(const double *Bm, int LD, int a, int b, double *c, double *s) {
-  const double apq = Bm[a * LD + b];
-  *c = 1.0;
-  *s = 0.0;
-  if (apq == 0.0) return;
-  const double tau = (Bm[b * LD + b] - Bm[a * LD + a]) * rcp_nr(2.0 * apq);
-  double t;
-  if (fabs(tau) > 1e150) {
-    t = 0.5 * rcp_nr(tau);
-  } else {
-    const double q = fma(tau, tau, 1.0);
-    const double r = rcp_nr(fabs(tau) + q * rsqrt_nr(q));
-    t = tau >= 0.0 ? r : -r;
-  }
-  *c = rsqrt_nr(fma(t, t, 1.0));
-  *s = t * *c;
+// Jacobi rotation of the pair (p, q) from b_pp, b_qq, b_pq, without branches:
+// tau = (b_qq - b_pp) / (2 b_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2))
+// (t = 1 / (2 tau) for |tau| > 1e18), c = 1 / sqrt(1 + t^2), s = t c. The
+// angle only needs to be close (a rotation then leaves b_pq times the angle's
+// relative error, which the next sweep removes), so t is formed in FP32 from
+// the FP64 difference b_qq - b_pp; c and s are FP64 functions of that t, so
+// c^2 + s^2 = 1 to FP64 rounding. The entries are scaled to magnitudes below
+// 1 by the caller; b_pq below FP32 range gives the identity.
+__device__ inline void jacobi_rot_bf(double app, double aqq, double apq, double *c, double *s) {
+  const float a = float(apq), d = float(aqq - app);
+  const bool nz = a != 0.0f;
+  const float tau = d * (0.5f * __builtin_amdgcn_rcpf(nz ? a : 1.0f));
+  const float at = fminf(fabsf(tau), 1e18f);
+  const float den = at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f));  // |tau| + sqrt(1 + tau^2)
+  float t = fabsf(tau) > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(fabsf(tau)) : __builtin_amdgcn_rcpf(den);
+  t = tau >= 0.0f ? t : -t;
+  const double td = double(t);
+  const double w = fma(td, td, 1.0);
+  const double h = 0.5 * w;
+  double y = __builtin_amdgcn_rsq(w);  // two Newton steps for 1 / sqrt(w)
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  *c = nz ? y : 1.0;
+  *s = nz ? td * y : 0.0;
 }
 
 // Round-robin pairing of ne (even) indices at a step: pair 0 = (ne-1, step),
@@ -444,45 +459,71 @@ __device__ inline void rr_pair(int ne, int step, int m, int *a, int *b) {
   }
 }
 
-// One workgroup: B = Q^T A Q restricted to the active columns, symmetrized;
-// cyclic Jacobi with round-robin ordering: the ne/2 disjoint rotations of a
-// step are computed first, then applied together in place, B' = J^T B J and
-// V' = V J. Eigenvalues sorted descending (stable); outputs the top k, their
-// eigenvectors in the RP basis, and FVE.
+// One workgroup: B = Q^T A Q on the active columns (symmetrized, placed first,
+// zero rows and columns for the rest), cyclic Jacobi with round-robin ordering
+// of all RP indices (a pair with an inactive index has a zero off-diagonal
+// and rotates by the identity). Thread (m1, m2) of the (RP/2)^2 threads owns
+// the 2x2 block (pair m1) x (pair m2) of B and the entries of V in rows m1 and
+// m1 + RP/2, pair m2: it computes rotation m2 from the current B and takes
+// rotation m1 from the lane of its wave that computed it (or computes it too
+// when RP/2 does not divide 64; every copy of a rotation has the same bits),
+// writes B' = J1^T X J2 into the other buffer and V' = V J in place, so a step
+// takes one barrier. Eigenvalues sorted descending (stable); outputs the top k,
+// their eigenvectors in the RP basis, and FVE.
 template <int RP>
-__global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, const int *__restrict__ act, int k,
-                                                double *__restrict__ evals, double *__restrict__ fve,
-                                                double *__restrict__ Uk) {
+__global__ __launch_bounds__((RP / 2) * (RP / 2)) void k_jacobi(const double *__restrict__ G,
+                                                                 const int *__restrict__ act, int k,
+                                                                 double *__restrict__ evals,
+                                                                 double *__restrict__ fve, double *__restrict__ Uk) {
+  constexpr int H = RP / 2;
+  constexpr int NT = H * H;
+  constexpr int NW = (NT + 63) / 64;
   constexpr int LD = RP + 1;
-  __shared__ double Bb[RP * LD];
+  __shared__ double Bb[2][RP * LD];
   __shared__ double Vb[RP * LD];
-  __shared__ double cs[RP / 2], sn[RP / 2];
-  __shared__ int pa[RP / 2], pb[RP / 2];
   __shared__ int idx[RP];
-  __shared__ int n_s, ne_s, stop;
-  __shared__ double red_off[JT / 64], red_tot[JT / 64];
+  __shared__ int n_s;
+  __shared__ double red_off[2][NW], red_tot[2][NW];
   const int tid = threadIdx.x;
   if (tid == 0) {
     int n = 0;
     for (int j = 0; j < RP; ++j)
       if (act[j]) idx[n++] = j;
     n_s = n;
-    ne_s = n + (n & 1);
   }
   __syncthreads();
-  const int n = n_s, ne = ne_s;
-  for (int e = tid; e < ne * ne; e += JT) {
-    const int a = e / ne, b = e % ne;
-    Bb[a * LD + b] = (a < n && b < n) ? 0.5 * (G[idx[a] * RP + idx[b]] + G[idx[b] * RP + idx[a]]) : 0.0;
+  const int n = n_s;
+  double mx = 0.0;
+  for (int e = tid; e < RP * RP; e += NT) {
+    const int a = e / RP, b = e % RP;
+    const double v = (a < n && b < n) ? 0.5 * (G[idx[a] * RP + idx[b]] + G[idx[b] * RP + idx[a]]) : 0.0;
+    Bb[0][a * LD + b] = v;
     Vb[a * LD + b] = (a == b) ? 1.0 : 0.0;
+    mx = fmax(mx, fabs(v));
   }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if ((tid & 63) == 0) red_off[1][tid >> 6] = mx;
   __syncthreads();
-  const int npair = ne / 2;
-  for (int sweep = 0; sweep < 60 && ne >= 2; ++sweep) {
+  // exact power-of-two scaling to max |B| in [0.5, 1); undone on the eigenvalues
+  mx = 0.0;
+  for (int wv = 0; wv < NW; ++wv) mx = fmax(mx, red_off[1][wv]);
+  int ex = 0;
+  if (mx > 0.0) frexp(mx, &ex);
+  for (int e = tid; e < RP * RP; e += NT) Bb[0][(e / RP) * LD + e % RP] = ldexp(Bb[0][(e / RP) * LD + e % RP], -ex);
+  __syncthreads();
+  const int m1 = tid / H, m2 = tid % H;
+  // step 0 pairs; every later step moves each index of a pair on by one
+  // (mod RP - 1), except index RP - 1 of pair 0
+  int a1, b1, a2, b2;
+  rr_pair(RP, 0, m1, &a1, &b1);
+  rr_pair(RP, 0, m2, &a2, &b2);
+  int cur = 0;
+  for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
+    // convergence: sum of squares off the diagonal against the total
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < ne * ne; e += JT) {
-      const int a = e / ne, b = e % ne;
-      const double v = Bb[a * LD + b] * Bb[a * LD + b];
+    for (int e = tid; e < RP * RP; e += NT) {
+      const int a = e / RP, b = e % RP;
+      const double v = Bb[cur][a * LD + b] * Bb[cur][a * LD + b];
       tot += v;
       if (a != b) off += v;
     }
@@ -491,69 +532,68 @@ __global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, con
       tot += __shfl_xor(tot, o);
     }
     if ((tid & 63) == 0) {
-      red_off[tid >> 6] = off;
-      red_tot[tid >> 6] = tot;
+      red_off[sweep & 1][tid >> 6] = off;
+      red_tot[sweep & 1][tid >> 6] = tot;
     }
     __syncthreads();
-    if (tid == 0) {
-      double so = 0.0, st = 0.0;
-      for (int wv = 0; wv < JT / 64; ++wv) {
-        so += red_off[wv];
-        st += red_tot[wv];
-      }
-      stop = !(so > 1e-28 * st);
+    double so = 0.0, st = 0.0;
+    for (int wv = 0; wv < NW; ++wv) {
+      so += red_off[sweep & 1][wv];
+      st += red_tot[sweep & 1][wv];
     }
-    __syncthreads();
-    if (stop) break;
-    for (int step = 0; step < ne - 1; ++step) {
-      if (tid < npair) {
-        int a, b;
-        rr_pair(ne, step, tid, &a, &b);
-        double c, s;
-        jacobi_rot(Bb, LD, a, b, &c, &s);
-        pa[tid] = a;
-        pb[tid] = b;
-        cs[tid] = c;
-        sn[tid] = s;
+    if (!(so > 1e-28 * st)) break;  // uniform: every thread summed the same partials
+    for (int step = 0; step < RP - 1; ++step) {
+      const double *B = Bb[cur];
+      double *Bn = Bb[cur ^ 1];
+      // every LDS read of the step is issued before the rotation is formed
+      const double x00 = B[a1 * LD + a2], x01 = B[a1 * LD + b2];
+      const double x10 = B[b1 * LD + a2], x11 = B[b1 * LD + b2];
+      double va[2], vb[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        va[h] = Vb[(m1 + h * H) * LD + a2];
+        vb[h] = Vb[(m1 + h * H) * LD + b2];
       }
-      __syncthreads();
-      // In place: the 2x2 block (rows of pair m1) x (columns of pair m2) of B
-      // depends only on itself, B' = J1^T X J2 with J = [[c, s], [-s, c]];
-      // V' = V J touches the two columns of one pair in one row.
-      const int nblk = npair * npair;
-      for (int e = tid; e < nblk + ne * npair; e += JT) {
-        if (e < nblk) {
-          const int m1 = e / npair, m2 = e % npair;
-          const int a1 = pa[m1], b1 = pb[m1], a2 = pa[m2], b2 = pb[m2];
-          const double c1 = cs[m1], s1 = sn[m1], c2 = cs[m2], s2 = sn[m2];
-          const double x00 = Bb[a1 * LD + a2], x01 = Bb[a1 * LD + b2];
-          const double x10 = Bb[b1 * LD + a2], x11 = Bb[b1 * LD + b2];
-          const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
-          const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
-          Bb[a1 * LD + a2] = c2 * y00 - s2 * y01;
-          Bb[a1 * LD + b2] = s2 * y00 + c2 * y01;
-          Bb[b1 * LD + a2] = c2 * y10 - s2 * y11;
-          Bb[b1 * LD + b2] = s2 * y10 + c2 * y11;
-        } else {
-          const int f = e - nblk;
-          const int row = f / npair, m = f % npair;
-          const int a = pa[m], b = pb[m];
-          const double c = cs[m], s = sn[m];
-          const double va = Vb[row * LD + a], vb = Vb[row * LD + b];
-          Vb[row * LD + a] = c * va - s * vb;
-          Vb[row * LD + b] = s * va + c * vb;
-        }
+      const double p22 = B[a2 * LD + a2], q22 = B[b2 * LD + b2], o22 = B[a2 * LD + b2];
+      asm volatile("" ::"v"(x00), "v"(x01), "v"(x10), "v"(x11), "v"(va[0]), "v"(vb[0]), "v"(va[1]), "v"(vb[1]));
+      double c1, s1, c2, s2;
+      jacobi_rot_bf(p22, q22, o22, &c2, &s2);
+      if constexpr (64 % H == 0) {
+        // rotation m1 is rotation m2 of lane (group of H lanes) + m1 of this wave
+        const int src = (threadIdx.x & 63 & ~(H - 1)) + m1;
+        c1 = __shfl(c2, src);
+        s1 = __shfl(s2, src);
+      } else {
+        jacobi_rot_bf(B[a1 * LD + a1], B[b1 * LD + b1], B[a1 * LD + b1], &c1, &s1);
       }
+      const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
+      const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
+      Bn[a1 * LD + a2] = c2 * y00 - s2 * y01;
+      Bn[a1 * LD + b2] = s2 * y00 + c2 * y01;
+      Bn[b1 * LD + a2] = c2 * y10 - s2 * y11;
+      Bn[b1 * LD + b2] = s2 * y10 + c2 * y11;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = m1 + h * H;
+        Vb[row * LD + a2] = c2 * va[h] - s2 * vb[h];
+        Vb[row * LD + b2] = s2 * va[h] + c2 * vb[h];
+      }
+      a1 = (m1 == 0) ? a1 : (a1 + 1 == RP - 1 ? 0 : a1 + 1);
+      a2 = (m2 == 0) ? a2 : (a2 + 1 == RP - 1 ? 0 : a2 + 1);
+      b1 = b1 + 1 == RP - 1 ? 0 : b1 + 1;
+      b2 = b2 + 1 == RP - 1 ? 0 : b2 + 1;
       __syncthreads();
+      cur ^= 1;
     }
   }
+  const double *Bf = Bb[cur];
   __shared__ int order[RP];
   __shared__ double possum;
   if (tid < n) {
-    const double v = Bb[tid * LD + tid];
+    const double v = Bf[tid * LD + tid];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double u = Bb[j * LD + j];
+      const double u = Bf[j * LD + j];
       if (u > v || (u == v && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -561,22 +601,22 @@ __global__ __launch_bounds__(JT) void k_jacobi(const double *__restrict__ G, con
   if (tid == 0) {
     double s = 0.0;
     for (int j = 0; j < n; ++j)
-      if (Bb[j * LD + j] > 0.0) s += Bb[j * LD + j];
+      if (Bf[j * LD + j] > 0.0) s += Bf[j * LD + j];
     possum = s;
   }
   __syncthreads();
   if (tid == 0) {
     double cum = 0.0;
     for (int l = 0; l < k; ++l) {
-      const double v = l < n ? Bb[order[l] * LD + order[l]] : 0.0;
+      const double v = l < n ? Bf[order[l] * LD + order[l]] : 0.0;
       cum += v;
-      evals[l] = v;
+      evals[l] = ldexp(v, ex);
       fve[l] = possum > 0.0 ? cum / possum : 0.0;
     }
   }
-  for (int e = tid; e < RP * k; e += JT) Uk[e] = 0.0;
+  for (int e = tid; e < RP * k; e += NT) Uk[e] = 0.0;
   __syncthreads();
-  for (int e = tid; e < n * k; e += JT) {
+  for (int e = tid; e < n * k; e += NT) {
     const int a = e / k, l = e % k;
     if (l < n) Uk[int64_t(idx[a]) * k + l] = Vb[a * LD + order[l]];
   }
@@ -685,7 +725,7 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
   size_t need = 2 * carve_bytes(P, 8) + carve_bytes(P * RP, sizeof(T)) + 3 * carve_bytes(P * RP, 8) +
                 carve_bytes(ngram * RP * RP, 8) + 2 * carve_bytes(RP * RP, 8) + carve_bytes(RP, 4) +
                 carve_bytes(RP * k, 8) +
-                2 * carve_bytes(k, 8) + carve_bytes(P * k, 8) + carve_bytes(nphi * k * 3, 8);
+                carve_bytes(2 * k, 8) + carve_bytes(P * k, 8) + carve_bytes(nphi * k * 3, 8);
   need += f32 ? carve_bytes(nsplit * P * RP, 4) : carve_bytes(P * RP, 8);
   if (int rc = ws_reserve(ctx, need)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
@@ -700,8 +740,8 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
   double *Rinv = cv.take<double>(RP * RP);
   int *act = cv.take<int>(RP);
   double *Uk = cv.take<double>(RP * k);
-  double *ev_d = cv.take<double>(k);
-  double *fve_d = cv.take<double>(k);
+  double *ev_d = cv.take<double>(2 * k);  // eigenvalues, then FVE: one copy to the host
+  double *fve_d = ev_d + k;
   double *phi = cv.take<double>(P * k);
   double *red = cv.take<double>(nphi * k * 3);
   float *part = f32 ? cv.take<float>(nsplit * P * RP) : nullptr;
@@ -790,16 +830,16 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
   hipLaunchKernelGGL(k_sum_gram<RP>, dim3(unsigned((RP * RP + 256 / SG - 1) / (256 / SG))), dim3(256), 0, ctx->stream,
                      int(ngram), gpart, G);
   FPCA_LAUNCH_CHECK("sum_gram");
-  hipLaunchKernelGGL(k_jacobi<RP>, dim3(1), dim3(JT), 0, ctx->stream, G, act, k, ev_d, fve_d, Uk);
+  hipLaunchKernelGGL(k_jacobi<RP>, dim3(1), dim3((RP / 2) * (RP / 2)), 0, ctx->stream, G, act, k, ev_d, fve_d, Uk);
   FPCA_LAUNCH_CHECK("jacobi");
   hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, RP, k, Q, Uk, w, phi,
                      red);
   FPCA_LAUNCH_CHECK("phi");
   hipLaunchKernelGGL(k_sign_write<T>, dim3(unsigned(k)), dim3(256), 0, ctx->stream, P, int(nphi), phi, red, efuns);
   FPCA_LAUNCH_CHECK("sign_write");
-  std::vector<double> hb(2 * k);
-  FPCA_HIP(hipMemcpyAsync(hb.data(), ev_d, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-  FPCA_HIP(hipMemcpyAsync(hb.data() + k, fve_d, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+  static_assert(fpca_context::kStageBytes >= 2 * 64 * sizeof(double), "staging holds 2k doubles for k <= 64");
+  double *hb = ctx->h_stage;
+  FPCA_HIP(hipMemcpyAsync(hb, ev_d, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, ctx->stream));
   FPCA_HIP(hipStreamSynchronize(ctx->stream));
   for (int l = 0; l < k; ++l) {
     evals_h[l] = hb[l];
