@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
                                                          const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
                                                          float *__restrict__ C, int64_t ldc, float alpha,
                                                          int zero_diag, int nb, SkPlan pl,
-                                                         float *__restrict__ part) {
+                                                         float *__restrict__ part, int vec4) {
   constexpr int BK = 32;
   constexpr int LR = BK + 8;  // padded LDS row in bf16 elements (80 bytes)
   __shared__ __attribute__((aligned(16))) unsigned short S[2][4][TB][LR];  // [buf][Ah Al Bh Bl][row][k]
@@ -348,21 +348,52 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
     }
     // D layout of a 16x16 MFMA block: lane l, element e -> row 4*(l/16)+e, column l%16
     if (slot < 0) {
+      // through LDS (free after the last step's barrier): rows of the tile and
+      // rows of its mirror leave as whole 512-byte rows
+      constexpr int LDT = TB + 1;
+      static_assert(sizeof(S) >= sizeof(float) * TB * LDT, "the epilogue tile fits in the staging buffers");
+      float *T = reinterpret_cast<float *>(&S[0][0][0][0]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t r = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
-            const int64_t c = n0 + wn * 64 + jj * 16 + (lane & 15);
-            if (r < N && c < N && (!diag_tile || r <= c)) {  // upper triangle and its mirror
-              float val = alpha * acc[i][jj][e];
-              if (zero_diag && r == c) val = 0.f;
-              C[r * ldc + c] = val;
-              if (r != c) C[c * ldc + r] = val;
-            }
+          for (int e = 0; e < 4; ++e)
+            T[(wm * 64 + i * 16 + 4 * (lane >> 4) + e) * LDT + wn * 64 + jj * 16 + (lane & 15)] =
+                alpha * acc[i][jj][e];
+      __syncthreads();
+      for (int q = tid; q < TB * (TB / 4); q += 256) {
+        const int a = q / (TB / 4), b4 = (q % (TB / 4)) * 4;
+        // direct: row m0 + a, columns n0 + b4 .. + 3 (upper triangle of a diagonal tile)
+        {
+          const int64_t r = m0 + a, c = n0 + b4;
+          float v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = (zero_diag && r == c + k) ? 0.f : T[a * LDT + b4 + k];
+          if (vec4 && !diag_tile && r < N && c + 3 < N) {
+            *reinterpret_cast<float4_t *>(C + r * ldc + c) = float4_t{v[0], v[1], v[2], v[3]};
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (r < N && c + k < N && (!diag_tile || a <= b4 + k)) C[r * ldc + c + k] = v[k];
           }
+        }
+        // mirror: row n0 + a, columns m0 + b4 .. + 3 (entries below a diagonal tile's diagonal)
+        {
+          const int64_t r = n0 + a, c = m0 + b4;
+          float v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = T[(b4 + k) * LDT + a];
+          if (vec4 && !diag_tile && r < N && c + 3 < N) {
+            *reinterpret_cast<float4_t *>(C + r * ldc + c) = float4_t{v[0], v[1], v[2], v[3]};
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (r < N && c + k < N && (!diag_tile || b4 + k < a)) C[r * ldc + c + k] = v[k];
+          }
+        }
+      }
+      __syncthreads();  // the next segment stages into the same LDS
     } else {
       float *dst = part + int64_t(slot) * (TB * TB) + (wm * 64 + 4 * (lane >> 4)) * TB + wn * 64 +
                    (lane & 15);
@@ -538,8 +569,9 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
     dim3 gs((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
     hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
     FPCA_LAUNCH_CHECK("split_t");
+    const int vec4 = (ldc % 4 == 0) && ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
     hipLaunchKernelGGL(k_syrk_bf16x3, dim3(unsigned(G)), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,
-                       int(zero_diag), nb, pl, part);
+                       int(zero_diag), nb, pl, part, vec4);
     FPCA_LAUNCH_CHECK("syrk_bf16x3");
     if (pl.W > 0) {
       hipLaunchKernelGGL(k_syrk_fixup, dim3(unsigned(2 * pl.W * (TB / FX_ROWS))), dim3(256), 0, ctx->stream, part, pl, nb, N,
