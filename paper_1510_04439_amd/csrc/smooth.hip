@@ -9,6 +9,7 @@
 // taps (1-u^2)u^j, j = 0..(remaining degree). This file holds the general
 // pass-per-coordinate engine for D <= 6 (partial moments in FP64 for either
 // storage type) and the per-node FP64 solve.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -36,17 +37,28 @@ struct MomArray {
   }
 };
 
-// One coordinate pass: o_j[e] = sum_m taps_j[m] src[e + m stride]. The source
-// is the FP32 or FP64 input on the first pass and an FP64 partial moment after
-// it; the partial moments and taps are FP64 so that the normal equations of
-// nearly degenerate windows (sparse bins, data on one side of the node) keep
-// their singular structure to FP64 rounding.
+// One coordinate pass over a batch of arrays (blockIdx.y = array a):
+// o_j[e] = sum_m taps_j[m] src_a[e + m stride]. The source is the FP32 or
+// FP64 input on the first pass and an FP64 partial moment after it; the
+// partial moments and taps are FP64 so that the normal equations of nearly
+// degenerate windows (sparse bins, data on one side of the node) keep their
+// singular structure to FP64 rounding.
+constexpr int MAXB = MAXMOM + 1;  // arrays in one pass
 template <typename TS>
-__global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int Mk, const TS *__restrict__ src,
-                                               int nj, double *__restrict__ o0, double *__restrict__ o1,
-                                               double *__restrict__ o2, const double *__restrict__ taps, int R) {
+struct PassBatch {
+  const TS *src[MAXB];
+  double *out[MAXB][3];
+  int nj[MAXB];
+};
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int Mk, PassBatch<TS> pb,
+                                               const double *__restrict__ taps, int R) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= total) return;
+  const int a = blockIdx.y;
+  const TS *__restrict__ src = pb.src[a];
+  const int nj = pb.nj[a];
   const int xk = int((e / stride) % Mk);
   const int lo = -min(R, xk), hi = min(R, Mk - 1 - xk);
   const int W = 2 * R + 1;
@@ -57,9 +69,9 @@ __global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int
     if (nj > 1) a1 = fma(taps[W + m + R], v, a1);
     if (nj > 2) a2 = fma(taps[2 * W + m + R], v, a2);
   }
-  o0[e] = a0;
-  if (nj > 1) o1[e] = a1;
-  if (nj > 2) o2[e] = a2;
+  pb.out[a][0][e] = a0;
+  if (nj > 1) pb.out[a][1][e] = a1;
+  if (nj > 2) pb.out[a][2][e] = a2;
 }
 
 struct MomPtrs {
@@ -134,15 +146,22 @@ __global__ void k_offdiag_fill(T *A, int64_t P, T v) {
 
 inline unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
 
-// taps[j][m + R] = (1 - u^2) u^j, u = m / (h (M-1)), 0 for |u| >= 1 (j = 0, 1, 2).
-__global__ void k_taps(double h, int M, int R, double *taps) {
-  const int W = 2 * R + 1;
+// taps of coordinate k (blockIdx.y) at ts.off[k]: [j][m + R] = (1 - u^2) u^j,
+// u = m / (h (M-1)), 0 for |u| >= 1 (j = 0, 1, 2).
+struct TapSpec {
+  double h[MAXD];
+  int M[MAXD], R[MAXD];
+  int64_t off[MAXD];
+};
+__global__ void k_taps(TapSpec ts, double *taps) {
+  const int k = blockIdx.y;
+  const int R = ts.R[k], W = 2 * R + 1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 3 * W) return;
   const int j = e / W, m = e % W - R;
-  const double u = double(m) / (h * double(M - 1));
+  const double u = double(m) / (ts.h[k] * double(ts.M[k] - 1));
   const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
-  taps[e] = K * (j == 0 ? 1.0 : (j == 1 ? u : u * u));
+  taps[ts.off[k] + e] = K * (j == 0 ? 1.0 : (j == 1 ? u : u * u));
 }
 
 // 1-D taps (1 - u^2) u^j at offsets m = -R..R, u = m / (h (M-1)), zero for |u| >= 1.
@@ -201,10 +220,18 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
   double *taps = cv.take<double>(tap_count);
   // tap tables are computed on the device (no host buffer in the stream: the
   // sequence can be captured into a graph)
-  for (int k = 0; k < D; ++k) {
-    const int W = 2 * R[k] + 1;
-    hipLaunchKernelGGL(k_taps, dim3(unsigned((3 * W + 255) / 256)), dim3(256), 0, ctx->stream, h[k], dims[k],
-                       R[k], taps + tap_off[k]);
+  {
+    TapSpec ts{};
+    int wmax = 1;
+    for (int k = 0; k < D; ++k) {
+      ts.h[k] = h[k];
+      ts.M[k] = dims[k];
+      ts.R[k] = R[k];
+      ts.off[k] = int64_t(tap_off[k]);
+      wmax = std::max(wmax, 2 * R[k] + 1);
+    }
+    hipLaunchKernelGGL(k_taps, dim3(unsigned((3 * wmax + 255) / 256), unsigned(D)), dim3(256), 0, ctx->stream, ts,
+                       taps);
     FPCA_LAUNCH_CHECK("taps");
   }
 
@@ -213,25 +240,33 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
     const int k = D - 1 - s;
     double *dst = (s % 2 == 0) ? bufA : bufB;
     std::vector<const double *> next;
+    PassBatch<T> b0{};      // first pass: the inputs, in their storage type
+    PassBatch<double> b1{};  // later passes: FP64 partial moments
+    const int na = int(lists[s].size());
+    if (na > MAXB) return set_error(FPCA_ERR_UNSUPPORTED, "too many moment arrays in one pass");
     size_t o = 0;
-    for (size_t a = 0; a < lists[s].size(); ++a) {
+    for (int a = 0; a < na; ++a) {
       const MomArray &m = lists[s][a];
       const int nj = (m.fam == 0 ? 2 : 1) - m.deg() + 1;
-      double *outs[3] = {nullptr, nullptr, nullptr};
-      for (int j = 0; j < nj; ++j) {
-        outs[j] = dst + (o + j) * size_t(total);
-        next.push_back(outs[j]);
+      for (int j = 0; j < 3; ++j) {
+        double *oj = j < nj ? dst + (o + j) * size_t(total) : nullptr;
+        if (j < nj) next.push_back(oj);
+        b0.out[a][j] = b1.out[a][j] = oj;
       }
-      double *o1 = outs[1] ? outs[1] : outs[0], *o2 = outs[2] ? outs[2] : outs[0];
-      if (s == 0)  // the inputs, in their storage type
-        hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k], dims[k],
-                           a == 0 ? w : g, nj, outs[0], o1, o2, taps + tap_off[k], R[k]);
+      b0.nj[a] = b1.nj[a] = nj;
+      if (s == 0)
+        b0.src[a] = a == 0 ? w : g;
       else
-        hipLaunchKernelGGL(k_pass<double>, dim3(nblk(total)), dim3(256), 0, ctx->stream, total, stride[k],
-                           dims[k], cur[a], nj, outs[0], o1, o2, taps + tap_off[k], R[k]);
-      FPCA_LAUNCH_CHECK("moment pass");
+        b1.src[a] = cur[a];
       o += nj;
     }
+    if (s == 0)
+      hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total, stride[k],
+                         dims[k], b0, taps + tap_off[k], R[k]);
+    else
+      hipLaunchKernelGGL(k_pass<double>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total,
+                         stride[k], dims[k], b1, taps + tap_off[k], R[k]);
+    FPCA_LAUNCH_CHECK("moment pass");
     cur.swap(next);
   }
   // Gather the final arrays in moment order.
