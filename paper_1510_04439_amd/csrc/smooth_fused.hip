@@ -4,13 +4,17 @@
 //  stage T: one workgroup per s-row of G (a whole t-plane, held in LDS): the
 //           t2 and t1 passes produce the partial moments G00, G10, G01
 //           (t-exponents).
-//  stage S: a workgroup owns 8 consecutive t columns, one wavefront per
+//  stage S: a workgroup owns 4 consecutive t columns, one wavefront per
 //           column, lane = s2. It streams the s1 rows of the partial moments
-//           through LDS, does the s2 pass of each row from LDS, keeps the
-//           last 2R+1 results in a register ring (row loop unrolled by 2R+1)
-//           for the s1 pass, and solves the 5x5 FP64 system per lane. Only nodes p <= q are
-//           computed (the surface is symmetric); each is written at (p,q)
-//           and (q,p) with mu(p)mu(q) subtracted and the domain mask applied.
+//           through LDS (double-buffered), does the s2 pass of each row from
+//           LDS, keeps the last 2R+1 results in a register window for the
+//           s1 pass, and forms b0 per lane: in closed form for nodes whose
+//           s- and t-windows share no grid node (the weight moments are then
+//           products of 1-D sums), by an FP64 solve after the row loop for
+//           the near-diagonal nodes (their response moments wait in LDS).
+//           Only nodes p <= q are computed (the surface is symmetric); each
+//           is written at (p,q) and (q,p) with mu(p)mu(q) subtracted and the
+//           domain mask applied.
 //
 // The pair weights are c0 (1 - delta_pq), so the 15 weight moments are exact
 // products of 1-D tap sums minus the diagonal part, evaluated in FP64 from
