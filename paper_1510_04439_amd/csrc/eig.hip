@@ -45,23 +45,25 @@ __global__ void k_normals(uint64_t seed, int64_t count, double *out) {
   for (; i < count; i += step) out[i] = normal_at(seed, uint64_t(i));
 }
 
-// X[p, j] = sqrt(w_p) Omega[p, j] (row-major P x rp, zero for j >= r).
+// Quadrature weights, their square roots and the scaled test matrix in one
+// pass, thread per (p, j): w_p = quad_w[p] if given, else the Riemann weight
+// wv (0 outside the mask); X[p][j] = sqrt(w_p) * normal number j*P + p of the
+// seed's stream for j < r, 0 for the padding columns.
 template <typename T>
-__global__ void k_test_matrix(uint64_t seed, int64_t P, int r, int rp, const double *__restrict__ w, T *X) {
-  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ void k_setup(uint64_t seed, int64_t P, int r, int rp, const double *__restrict__ quad_w, double wv,
+                        const uint8_t *__restrict__ mask, double *__restrict__ w, double *__restrict__ sw, T *X) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= P * rp) return;
   const int64_t p = e / rp;
   const int j = int(e % rp);
-  double v = 0.0;
-  if (j < r) v = sqrt(w[p]) * normal_at(seed, uint64_t(j) * uint64_t(P) + uint64_t(p));
-  X[e] = T(v);
+  const double wp = quad_w ? quad_w[p] : ((mask && !mask[p]) ? 0.0 : wv);
+  const double s = sqrt(wp);
+  if (j == 0) {
+    w[p] = wp;
+    sw[p] = s;
+  }
+  X[e] = T(j < r ? s * normal_at(seed, uint64_t(j) * uint64_t(P) + uint64_t(p)) : 0.0);
 }
-
-__global__ void k_default_w(int64_t P, double wv, const uint8_t *mask, double *w) {
-  int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < P) w[p] = (mask && !mask[p]) ? 0.0 : wv;
-}
-
 
 // Partial products of Y^T = X^T Gamma over one K chunk (Gamma symmetric):
 // workgroup = (64 nodes, K chunk); 4 wavefronts x 16 nodes; MFMA 16x16x4 FP32
@@ -667,19 +669,35 @@ __global__ __launch_bounds__(256) void k_sign_write(int64_t P, int nblk, const d
   __shared__ double S1, S2, MX;
   __shared__ long long first[256];
   const int l = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) {
+  {
+    // the workgroups' partials: thread t adds t, t + 256, ...; then a fixed tree
+    __shared__ double ra[256], rb[256], rm[256];
     double a = 0.0, b = 0.0, m = 0.0;
-    for (int i = 0; i < nblk; ++i) {
+    for (int i = tid; i < nblk; i += 256) {
       const int64_t o = (int64_t(l) * nblk + i) * 3;
       a += red[o];
       b += red[o + 1];
       m = fmax(m, red[o + 2]);
     }
-    S1 = a;
-    S2 = b;
-    MX = m;
+    ra[tid] = a;
+    rb[tid] = b;
+    rm[tid] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) {
+        ra[tid] += ra[tid + st];
+        rb[tid] += rb[tid + st];
+        rm[tid] = fmax(rm[tid], rm[tid + st]);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      S1 = ra[0];
+      S2 = rb[0];
+      MX = rm[0];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const double *f = phi + int64_t(l) * P;
   bool neg;
   if (fabs(S1) >= 1e-8 * S2) {
@@ -704,11 +722,6 @@ __global__ __launch_bounds__(256) void k_sign_write(int64_t P, int nblk, const d
 }
 
 inline unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
-
-__global__ void k_sqrt(int64_t P, const double *__restrict__ w, double *__restrict__ sw) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < P) sw[p] = sqrt(w[p]);
-}
 
 template <typename T, int RP>
 int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k, int r,
@@ -747,18 +760,13 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
   float *part = f32 ? cv.take<float>(nsplit * P * RP) : nullptr;
   double *Yraw = f32 ? nullptr : cv.take<double>(P * RP);
 
-  if (quad_w) {
-    FPCA_HIP(hipMemcpyAsync(w, quad_w, sizeof(double) * P, hipMemcpyDeviceToDevice, ctx->stream));
-  } else {
+  {
     double wv = 1.0;
     for (int q = 0; q < grid->d; ++q) wv /= double(grid->M[q] - 1);
-    hipLaunchKernelGGL(k_default_w, dim3(nb(P)), dim3(256), 0, ctx->stream, P, wv, grid->mask, w);
-    FPCA_LAUNCH_CHECK("default_w");
+    hipLaunchKernelGGL(k_setup<T>, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, seed, P, r, RP, quad_w, wv,
+                       grid->mask, w, sw, X);
+    FPCA_LAUNCH_CHECK("setup");
   }
-  hipLaunchKernelGGL(k_sqrt, dim3(nb(P)), dim3(256), 0, ctx->stream, P, w, sw);
-  FPCA_LAUNCH_CHECK("sqrt_w");
-  hipLaunchKernelGGL(k_test_matrix<T>, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, seed, P, r, RP, w, X);
-  FPCA_LAUNCH_CHECK("test_matrix");
 
   // Y (or Z) = W^1/2 Gamma X, then the partial Gram into gA (MODE 1: of itself, MODE 2: Q^T Y)
   auto product = [&](double *out, int mode) -> int {
