@@ -168,11 +168,12 @@ def test_bin_cov_common_grid(torch, F, h, prec, tol, M):
     assert normwise_rel(host(s2), rs2) < 1e-5
 
 
-@pytest.mark.parametrize("M,n", [((64, 64), 5000), ((64, 70), 3001), ((64, 96), 1000)])
+@pytest.mark.parametrize("M,n", [((64, 64), 5000), ((64, 70), 3001), ((64, 96), 1000), ((61, 71), 777)])
 def test_bin_cov_common_grid_bf16x3_full(torch, F, h, M, n):
     """BF16x3 Gram product at full size, where the upper-triangle tiles outnumber
     the resident workgroups and the last tiles are split along the curves
-    (K ragged for n = 3001): sampled entries and whole rows against the oracle's
+    (K ragged for n = 3001 and 777; P = 4331 is odd, so the tile rows leave
+    without vector stores): sampled entries and whole rows against the oracle's
     per-entry sums; exact symmetry and a zero diagonal over the whole matrix."""
     _say(f"bin_cov common bf16x3 full M={M} n={n}")
     rng = np.random.default_rng(17)
@@ -389,6 +390,45 @@ def test_eig_closed_form_and_oracle(torch, F, h):
             err = min(np.abs(phi[:, j] - rphi[:, j]).max(), np.abs(phi[:, j] + rphi[:, j]).max())
             assert err <= 100 * tol * np.abs(rphi[:, j]).max(), (dt, j, err)
         np.testing.assert_allclose(ev, lam, rtol=2e-3)
+
+
+@pytest.mark.parametrize("k,p,dt,rank", [(6, 24, "f32", 0), (8, 32, "f32", 0), (10, 54, "f32", 0),
+                                          (8, 32, "f64", 0), (10, 54, "f64", 0), (6, 24, "f32", 12),
+                                          (10, 38, "f32", 20)])
+def test_eig_basis_widths(torch, F, h, k, p, dt, rank):
+    """Basis widths r = k + p of 30, 40 and 64 (the 32-, 48- and 64-column
+    Cholesky and Jacobi kernels; at 48 every thread forms both of its
+    rotations), against the oracle's randomized eig. rank > 0: the surface has
+    that rank, so the orthonormalizations drop columns."""
+    _say(f"eig widths k={k} p={p} {dt} rank={rank}")
+    M = (24, 20)
+    P = 480
+    rng = np.random.default_rng(40 + k + p + rank)
+    nv = rank if rank else 60
+    V = np.linalg.qr(rng.standard_normal((P, nv)))[0]
+    lam = 1.5 ** -np.arange(nv)
+    Gam = (V * lam) @ V.T
+    if not rank:
+        E = rng.standard_normal((P, P)) * 1e-6
+        Gam = Gam + (E + E.T) / 2
+    om = oracle.quad_weights(M, rule="trapezoid")
+    npdt = np.float64 if dt == "f64" else np.float32
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    ef = torch.empty(k, P, dtype=tdt, device="cuda:0")
+    ev, fve = F.fpca_eig_randomized(h, F.FPCA_F64 if dt == "f64" else F.FPCA_F32,
+                                    F.FPCA_PREC_F64 if dt == "f64" else F.FPCA_PREC_F32, F.Grid(M),
+                                    dev(torch, Gam.astype(npdt)), dev(torch, om), k, p, 2, 11, ef)
+    rev, rphi, rfve = oracle.eig_randomized(Gam.astype(npdt).astype(np.float64), om, k, p, 2, 11)
+    tol = 1e-10 if dt == "f64" else 1e-5
+    assert np.abs(ev - rev).max() <= tol * np.abs(rev).max()
+    assert np.abs(fve - rfve).max() <= tol
+    phi = host(ef).T
+    for j in range(k):
+        # eigenvector tolerance scales with the gap to the neighbouring eigenvalues
+        gap = min(abs(rev[j] - rev[j - 1]) if j else np.inf, abs(rev[j] - rev[j + 1]) if j + 1 < k else np.inf)
+        scale = max(1.0, 0.1 * rev[0] / gap) if np.isfinite(gap) else 1.0
+        err = min(np.abs(phi[:, j] - rphi[:, j]).max(), np.abs(phi[:, j] + rphi[:, j]).max())
+        assert err <= 100 * tol * scale * np.abs(rphi[:, j]).max(), (j, err)
 
 
 def test_eig_riemann_default_weights_and_mask(torch, F, h):
