@@ -168,28 +168,50 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
 // Precision split for the BF16x3 product: A (K x N row-major FP32) ->
 // Th = bf16(A^T), Tl = bf16(A^T - Th), both N x Kp with K contiguous and the
 // rows padded with zeros to Kp (a multiple of 32). 64x64 tiles through LDS.
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
 __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, int64_t K, int64_t N, int64_t Kp,
                                                   unsigned short *__restrict__ Th, unsigned short *__restrict__ Tl) {
   __shared__ float tile[64][65];
   const int64_t n0 = int64_t(blockIdx.x) * 64, k0 = int64_t(blockIdx.y) * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t k = k0 + r, n = n0 + tx;
-    tile[r][tx] = (k < K && n < N) ? A[k * N + n] : 0.f;
+  // 16 threads per input row, four consecutive n each (16-byte loads where aligned)
+  const int q4 = (threadIdx.x & 15) * 4, ty = threadIdx.x >> 4;
+  const bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  for (int r = ty; r < 64; r += 16) {
+    const int64_t k = k0 + r, n = n0 + q4;
+    if (vec && k < K && n + 3 < N) {
+      const float4 v = *reinterpret_cast<const float4 *>(A + k * N + n);
+      tile[r][q4] = v.x;
+      tile[r][q4 + 1] = v.y;
+      tile[r][q4 + 2] = v.z;
+      tile[r][q4 + 3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tile[r][q4 + e] = (k < K && n + e < N) ? A[k * N + n + e] : 0.f;
+    }
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t n = n0 + r, k = k0 + tx;
-    if (n < N && k < Kp) {
-      const float x = tile[tx][r];
-      const unsigned short h = bf16_rne(x);
-      Th[n * Kp + k] = h;
-      Tl[n * Kp + k] = bf16_rne(x - bf16_to_f32(h));
+  // thread -> output row n0 + tid/4, two runs of eight k (16-byte stores)
+  const int rn = threadIdx.x >> 2;
+  const int64_t n = n0 + rn;
+  if (n >= N) return;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = (threadIdx.x & 3) * 2 + h;  // run c: k = k0 + 8c .. + 7
+    if (k0 + 8 * c >= Kp) continue;           // Kp is a multiple of 32, runs are whole
+    u16x8 hv, lv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float x = tile[8 * c + e][rn];
+      const unsigned short hb = bf16_rne(x);
+      hv[e] = hb;
+      lv[e] = bf16_rne(x - bf16_to_f32(hb));
     }
+    *reinterpret_cast<u16x8 *>(Th + n * Kp + k0 + 8 * c) = hv;
+    *reinterpret_cast<u16x8 *>(Tl + n * Kp + k0 + 8 * c) = lv;
   }
 }
 
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Work split of the persistent SYRK (all tile numbers in band order, S K
