@@ -31,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFS = 2500.0  # dense BF16 matrix peak of one MI355X
 
 
 def log(msg):
@@ -239,6 +240,10 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = nodes / (ms_per_step / 1e3)
     sc_ms = stage_ms["smooth_cov"]
+    # the Gram product Y^T Y of the covariance binning: 2 n P^2 flop as a full
+    # product (each 128x128 tile on or above the diagonal runs three BF16 products)
+    Pc = int(np.prod(ds.M_cov))
+    gram_flops = 2.0 * args.n * Pc * Pc
     alg_bytes = 12.0 * nodes  # read C and G, write gamma: 4 B each per node
     achieved = alg_bytes / (sc_ms / 1e3) / 1e9
     out = {
@@ -263,6 +268,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (k_tables, k_stage_t, k_stage_s)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "alg_bytes_per_node": 12},
+        "roofline_gram": {"bound": "mfma", "kernel": "fpca_bin COV (k_split_t, k_syrk_bf16x3, k_syrk_fixup)",
+                          "achieved": gram_flops / (stage_ms["bin_cov"] / 1e3) / 1e12, "peak": BF16_PEAK_TFS,
+                          "unit": "TFLOP/s", "frac": gram_flops / (stage_ms["bin_cov"] / 1e3) / 1e12 / BF16_PEAK_TFS,
+                          "alg_flops": gram_flops, "mfma_flops": 3 * gram_flops * (Pc + 128) / (2 * Pc)},
         "evals_top3": [float(v) for v in bufs.evals[:3]],
     }
     out["hselect"] = None if args.no_hselect else hselect_timing(h, torch)
