@@ -193,7 +193,9 @@ int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const 
  * rescaled as phi = psi / sqrt(w) so that sum_p w_p phi_p^2 = 1, with the sign
  * chosen so that sum_p w_p phi_p > 0 (if that sum is below 1e-8 sum_p w_p |phi_p|,
  * the lowest-index entry within a relative 1e-6 of max |phi| is made positive).
- * fve[l] = sum_{m<=l} theta_m / sum of the positive theta over all r Ritz values.
+ * fve[l] = sum_{m<=l} theta_m / sum of the positive theta over all r Ritz values
+ * (0 when no Ritz value is positive). Beyond the numerical rank (fewer kept
+ * basis columns than k) the eigenvalues and eigenfunctions are 0.
  * Test matrix: entry (p, j) is standard normal number j*P + p of stream `seed`,
  * drawn by the Box-Muller cosine branch from two splitmix64 outputs.
  *   gamma: P x P (P = prod grid->M) symmetric, `dtype`.

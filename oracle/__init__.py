@@ -386,7 +386,8 @@ def eig_randomized(gamma, omega, k, oversample, power_iters, seed, return_basis=
     th = th[order]
     U = U[:, order]
     pos = th[th > 0].sum()
-    fve = np.cumsum(th[:k]) / pos
+    # no positive Ritz value (e.g. a zero surface): the ratio is undefined; 0 by convention
+    fve = np.cumsum(th[:k]) / pos if pos > 0 else np.zeros(k)
     phi = _rescale_and_sign(Q @ U[:, :k], omega)
     if return_basis:
         return th[:k], phi, fve, Q

@@ -431,6 +431,31 @@ def test_eig_basis_widths(torch, F, h, k, p, dt, rank):
         assert err <= 100 * tol * scale * np.abs(rphi[:, j]).max(), (j, err)
 
 
+def test_eig_degenerate_surfaces(torch, F, h):
+    """A zero surface (every basis column dropped: eigenvalues, FVE and
+    eigenfunctions 0) and a rank-one surface (one eigenpair, the rest 0; FVE 1)."""
+    _say("eig degenerate")
+    M = (8, 8)
+    P = 64
+    om = oracle.quad_weights(M)
+    x = np.arange(P) / P
+    for name, Gam in (("zero", np.zeros((P, P))), ("rank1", np.outer(x, x))):
+        ef = torch.empty(3, P, dtype=torch.float64, device="cuda:0")
+        ev, fve = F.fpca_eig_randomized(h, F.FPCA_F64, F.FPCA_PREC_F64, F.Grid(M), dev(torch, Gam), dev(torch, om),
+                                        3, 5, 1, 3, ef)
+        phi = host(ef).T
+        rev, rphi, rfve = oracle.eig_randomized(Gam, om, 3, 5, 1, 3)
+        assert np.all(np.isfinite(ev)) and np.all(np.isfinite(fve)) and np.all(np.isfinite(phi))
+        assert np.abs(ev - rev).max() <= 1e-10 * max(1.0, np.abs(rev).max()), name
+        assert np.abs(fve - rfve).max() <= 1e-10, name
+        if name == "zero":
+            assert np.all(ev == 0) and np.all(phi == 0)
+        else:
+            err = min(np.abs(phi[:, 0] - rphi[:, 0]).max(), np.abs(phi[:, 0] + rphi[:, 0]).max())
+            assert err <= 1e-8 * np.abs(rphi[:, 0]).max()
+            assert np.all(phi[:, 1:] == 0) and np.all(ev[1:] == 0)
+
+
 def test_eig_riemann_default_weights_and_mask(torch, F, h):
     _say("eig default weights")
     M = (8, 8, 8)
