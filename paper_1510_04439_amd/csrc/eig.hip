@@ -626,7 +626,8 @@ __global__ __launch_bounds__((RP / 2) * (RP / 2)) void k_jacobi(const double *__
 
 // phi[l][p] = (Q U)[p][l] / sqrt(w_p) (0 where w_p = 0), with per-workgroup
 // partial sums of w phi, w |phi| and max |phi| for the sign rule.
-__global__ __launch_bounds__(256) void k_phi(int64_t P, int rp, int k, const double *__restrict__ Q,
+template <int RP>
+__global__ __launch_bounds__(256) void k_phi(int64_t P, int k, const double *__restrict__ Q,
                                               const double *__restrict__ Uk, const double *__restrict__ w,
                                               double *__restrict__ phi, double *__restrict__ red) {
   __shared__ double r1[4], r2[4], r3[4];
@@ -635,7 +636,8 @@ __global__ __launch_bounds__(256) void k_phi(int64_t P, int rp, int k, const dou
   double f = 0.0, wp = 0.0;
   if (p < P) {
     double v = 0.0;
-    for (int i = 0; i < rp; ++i) v += Q[p * rp + i] * Uk[int64_t(i) * k + l];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) v += Q[p * RP + i] * Uk[int64_t(i) * k + l];  // the row's loads all in flight
     wp = w[p];
     f = wp > 0.0 ? v / sqrt(wp) : 0.0;
     phi[int64_t(l) * P + p] = f;
@@ -718,6 +720,7 @@ __global__ __launch_bounds__(256) void k_sign_write(int64_t P, int nblk, const d
     neg = first[0] < P && f[first[0]] < 0.0;
   }
   const double sg = neg ? -1.0 : 1.0;
+#pragma unroll 8
   for (int64_t p = tid; p < P; p += 256) efuns[int64_t(l) * P + p] = T(sg * f[p]);
 }
 
@@ -840,7 +843,7 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
   FPCA_LAUNCH_CHECK("sum_gram");
   hipLaunchKernelGGL(k_jacobi<RP>, dim3(1), dim3((RP / 2) * (RP / 2)), 0, ctx->stream, G, act, k, ev_d, fve_d, Uk);
   FPCA_LAUNCH_CHECK("jacobi");
-  hipLaunchKernelGGL(k_phi, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, RP, k, Q, Uk, w, phi,
+  hipLaunchKernelGGL(k_phi<RP>, dim3(unsigned(nphi), unsigned(k)), dim3(256), 0, ctx->stream, P, k, Q, Uk, w, phi,
                      red);
   FPCA_LAUNCH_CHECK("phi");
   hipLaunchKernelGGL(k_sign_write<T>, dim3(unsigned(k)), dim3(256), 0, ctx->stream, P, int(nphi), phi, red, efuns);

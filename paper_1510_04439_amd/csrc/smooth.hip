@@ -63,7 +63,20 @@ __global__ __launch_bounds__(256) void k_pass(int64_t total, int64_t stride, int
   const int lo = -min(R, xk), hi = min(R, Mk - 1 - xk);
   const int W = 2 * R + 1;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int m = lo; m <= hi; ++m) {
+  // four taps' loads in flight at a time; the sums run in tap order
+  int m = lo;
+  for (; m + 3 <= hi; m += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = double(src[e + int64_t(m + u) * stride]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0 = fma(taps[m + u + R], v[u], a0);
+      if (nj > 1) a1 = fma(taps[W + m + u + R], v[u], a1);
+      if (nj > 2) a2 = fma(taps[2 * W + m + u + R], v[u], a2);
+    }
+  }
+  for (; m <= hi; ++m) {
     const double v = double(src[e + int64_t(m) * stride]);
     a0 = fma(taps[m + R], v, a0);
     if (nj > 1) a1 = fma(taps[W + m + R], v, a1);
