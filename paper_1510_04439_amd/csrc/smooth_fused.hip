@@ -66,6 +66,10 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
   const int M = k == 0 ? M0 : M1;
   const double H = k == 0 ? H0 : H1;
   const int R = k == 0 ? R0 : R1;
+  // u = m / H for the offsets m = -R .. R (R <= RMAX), divided once per workgroup
+  __shared__ double uo[2 * RMAX + 1];
+  if (int(threadIdx.x) <= 2 * R) uo[threadIdx.x] = double(int(threadIdx.x) - R) / H;
+  __syncthreads();
   if (k == 0) {
     // the first coordinate's factors of the tensor-product fit (m = W1/W0,
     // e = W2/W0, v = e - m^2), one node per thread
@@ -74,7 +78,7 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
       if (x < M)
         for (int m = -R; m <= R; ++m) {
           if (x + m < 0 || x + m >= M) continue;
-          const double u = double(m) / H;
+          const double u = uo[m + R];
           const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
           w[0] += K;
           w[1] += K * u;
@@ -98,7 +102,7 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
       if (x < M)
         for (int m = -R; m <= R; ++m) {
           if (x + m < 0 || x + m >= M) continue;
-          const double u = double(m) / H;
+          const double u = uo[m + R];
           const double K = fabs(u) < 1.0 ? 1.0 - u * u : 0.0;
           s += K * (ex == 0 ? 1.0 : (ex == 1 ? u : u * u));
         }
@@ -113,7 +117,7 @@ __global__ void k_tables(int M0, int M1, double H0, double H1, int R0, int R1, i
       // only nodes within R of both i and j contribute
       if (i < M && j < M)
         for (int y = max(0, max(i, j) - R); y <= min(M - 1, min(i, j) + R); ++y) {
-          const double ui = double(y - i) / H, uj = double(y - j) / H;
+          const double ui = uo[y - i + R], uj = uo[y - j + R];
           const double Ki = fabs(ui) < 1.0 ? 1.0 - ui * ui : 0.0;
           const double Kj = fabs(uj) < 1.0 ? 1.0 - uj * uj : 0.0;
           if (Ki == 0.0 || Kj == 0.0) continue;
@@ -476,7 +480,7 @@ int smooth_cov_fused_d2(fpca_context *ctx, const fpca_grid *grid, double c0, con
   double *Dt = cv.take<double>(2 * 6 * size_t(Mmax) * Mmax);
   double *Xt = cv.take<double>(4 * size_t(Mmax));
   const double H2 = bw[1] * double(M2 - 1);
-  hipLaunchKernelGGL(k_tables, dim3(64, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2), Mmax,
+  hipLaunchKernelGGL(k_tables, dim3(128, 2), dim3(256), 0, ctx->stream, M1, M2, H, H2, R, tap_radius(bw[1], M2), Mmax,
                      Wt, Dt, Xt);
   FPCA_LAUNCH_CHECK("tables");
   tab.W = Wt;
