@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
 
 // Precision split for the BF16x3 product: A (K x N row-major FP32) ->
 // Th = bf16(A^T), Tl = bf16(A^T - Th), both N x Kp with K contiguous and the
-// rows padded with zeros to Kp (a multiple of 32). 64x64 tiles through LDS.
+// rows padded with zeros to Kp (a multiple of 64). 64x64 tiles through LDS.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, int64_t K, int64_t N, int64_t Kp,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, in
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int c = (threadIdx.x & 3) * 2 + h;  // run c: k = k0 + 8c .. + 7
-    if (k0 + 8 * c >= Kp) continue;           // Kp is a multiple of 32, runs are whole
+    if (k0 + 8 * c >= Kp) continue;           // Kp is a multiple of 64, runs are whole
     u16x8 hv, lv;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, in
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Work split of the persistent SYRK (all tile numbers in band order, S K
-// steps per tile, G workgroups, tiles = F G + W with 0 <= W < G):
+// steps of 64 per tile, G workgroups, tiles = F G + W with 0 <= W < G):
 //  - "whole" tiles 0 .. D-1, D = tiles - 2W (or all tiles when W = 0): wave f
 //    gives workgroup w the tile f G + slot(w), slot(w) = (w % 8) (G / 8) + w / 8,
 //    so the tiles of one XCD are a contiguous run; every whole tile starts at
@@ -248,8 +248,10 @@ __device__ inline int64_t sk_end(const SkPlan &pl, int u) {
 }
 
 // C = alpha * A^T A from the split operands; tiles of 128x128 on or above the
-// diagonal (mirrored), 4 wavefronts of 64x64, K steps of 32 through double-
-// buffered LDS. Per 16x16 block and K step: lo*hi + hi*lo + hi*hi on
+// diagonal (mirrored), 4 wavefronts of 64x64. K goes through LDS 64 at a time
+// (the next 64 wait in registers) as two MFMA k-steps of 32, the second
+// step's operands read while the first step's MFMAs run. Per 16x16 block and
+// k-step: lo*hi + hi*lo + hi*hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the lo*lo term, below
 // 2^-16 of the product, is dropped). Whole tiles are written to C; a piece of
 // a split tile leaves its accumulators in its partial slot for k_syrk_fixup.
@@ -258,9 +260,10 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
                                                          float *__restrict__ C, int64_t ldc, float alpha,
                                                          int zero_diag, int nb, SkPlan pl,
                                                          float *__restrict__ part, int vec4) {
-  constexpr int BK = 32;
-  constexpr int LR = BK + 8;  // padded LDS row in bf16 elements (80 bytes)
-  __shared__ __attribute__((aligned(16))) unsigned short S[2][4][TB][LR];  // [buf][Ah Al Bh Bl][row][k]
+  constexpr int BK = 64;       // K per LDS fill: two MFMA k-steps of 32
+  constexpr int LR = BK + 8;   // padded LDS row in bf16 elements (144 bytes)
+  // one fill [Ah Al Bh Bl][row][k]; the next fill waits in registers
+  __shared__ __attribute__((aligned(16))) unsigned short S[4][TB][LR];
   const int w = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -297,8 +300,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) acc[i][jj] = float4_t{0.f, 0.f, 0.f, 0.f};
-    // staging: 128 rows x 4 chunks of 16 bytes per array; 2 chunks per thread
-    u16x8 st[4][2];
+    // staging: 128 rows x 8 chunks of 16 bytes per array; 4 chunks per thread
+    u16x8 st[4][4];
     auto load = [&](int64_t kb) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -306,9 +309,9 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
         const unsigned short *src = (a & 1) ? Tl : Th;
         const int64_t r0 = (a < 2) ? m0 : n0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 4; ++h) {
           const int c = tid + 256 * h;
-          const int row = c >> 2, pt = c & 3;
+          const int row = c >> 3, pt = c & 7;
           const int64_t gr = r0 + row;
           if (gr < N)
             st[a][h] = *reinterpret_cast<const u16x8 *>(src + gr * Kp + kb + pt * 8);
@@ -317,38 +320,33 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
         }
       }
     };
-    auto store = [&](int buf) {
+    auto store = [&]() {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (a >= narr) break;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 4; ++h) {
           const int c = tid + 256 * h;
-          *reinterpret_cast<u16x8 *>(&S[buf][a][c >> 2][(c & 3) * 8]) = st[a][h];
+          *reinterpret_cast<u16x8 *>(&S[a][c >> 3][(c & 7) * 8]) = st[a][h];
         }
       }
     };
     const int bh = diag_tile ? 0 : 2, bl = diag_tile ? 1 : 3;
-    const int64_t kb0 = int64_t(k0) * BK, kb1 = int64_t(k1) * BK;
-    int buf = 0;
-    load(kb0);
-    store(0);
-    __syncthreads();
-    for (int64_t kb = kb0; kb < kb1; kb += BK) {
-      const bool more = kb + BK < kb1;
-      if (more) load(kb + BK);
-      bf16x8 ah[4], al[4], bhv[4], blv[4];
+    // operands of the k-step at offset ks of the fill
+    auto frag = [&](int ks, bf16x8 *ah, bf16x8 *al, bf16x8 *bhv, bf16x8 *blv) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = wm * 64 + i * 16 + (lane & 15);
-        ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][0][r][kq]));
-        al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][1][r][kq]));
+        ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[0][r][ks + kq]));
+        al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[1][r][ks + kq]));
         const int c = wn * 64 + i * 16 + (lane & 15);
-        bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bh][c][kq]));
-        blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][bl][c][kq]));
+        bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[bh][c][ks + kq]));
+        blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[bl][c][ks + kq]));
       }
-      // the three products of a block are 16 MFMAs apart (independent
-      // accumulators in between), so no MFMA waits on its predecessor
+    };
+    // the three products of a block are 16 MFMAs apart (independent
+    // accumulators in between), so no MFMA waits on its predecessor
+    auto mma = [&](const bf16x8 *ah, const bf16x8 *al, const bf16x8 *bhv, const bf16x8 *blv) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -364,9 +362,20 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[jj], acc[i][jj], 0, 0, 0);
-      if (more) store(buf ^ 1);
+    };
+    const int64_t kb0 = int64_t(k0) * BK, kb1 = int64_t(k1) * BK;
+    load(kb0);
+    for (int64_t kb = kb0; kb < kb1; kb += BK) {
+      store();
       __syncthreads();
-      buf ^= 1;
+      if (kb + BK < kb1) load(kb + BK);
+      // the second k-step's operands are read while the first k-step's MFMAs run
+      bf16x8 a0h[4], a0l[4], b0h[4], b0l[4], a1h[4], a1l[4], b1h[4], b1l[4];
+      frag(0, a0h, a0l, b0h, b0l);
+      frag(32, a1h, a1l, b1h, b1l);
+      mma(a0h, a0l, b0h, b0l);
+      mma(a1h, a1l, b1h, b1l);
+      __syncthreads();  // the next fill overwrites S
     }
     // D layout of a 16x16 MFMA block: lane l, element e -> row 4*(l/16)+e, column l%16
     if (slot < 0) {
@@ -374,7 +383,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
       // rows of its mirror leave as whole 512-byte rows
       constexpr int LDT = TB + 1;
       static_assert(sizeof(S) >= sizeof(float) * TB * LDT, "the epilogue tile fits in the staging buffers");
-      float *T = reinterpret_cast<float *>(&S[0][0][0][0]);
+      float *T = reinterpret_cast<float *>(&S[0][0][0]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -554,8 +563,8 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
   const unsigned grid = unsigned(per) * XCDS;
   bool vec = (N % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   if (prec == FPCA_PREC_BF16X3) {
-    const int64_t Kp = ((K + 31) / 32) * 32;
-    const int64_t nsteps = Kp / 32;
+    const int64_t Kp = ((K + 63) / 64) * 64;
+    const int64_t nsteps = Kp / 64;
     // persistent workgroups: two per CU, a multiple of the XCD count
     int G = 2 * ctx->num_cus;
     G = (G / XCDS) * XCDS;
