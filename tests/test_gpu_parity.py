@@ -431,6 +431,34 @@ def test_eig_basis_widths(torch, F, h, k, p, dt, rank):
         assert err <= 100 * tol * scale * np.abs(rphi[:, j]).max(), (j, err)
 
 
+def test_eig_full_size(torch, F, h):
+    """The benchmark's eig configuration at its full size: P = 64^2 = 4096 nodes,
+    k = 20, oversample 10, two power iterations, FP32 surface (the launch
+    configuration of the benchmark: 32-column basis, 16-way K split of the
+    products), against the oracle's FP64 randomized eig on the same surface."""
+    _say("eig full size P=4096 k=20 p=10 q=2")
+    M = (64, 64)
+    P = 4096
+    rng = np.random.default_rng(77)
+    nv = 200
+    V = np.linalg.qr(rng.standard_normal((P, nv)))[0]
+    lam = (1.0 + np.arange(nv)) ** -2.0
+    Gam = ((V * lam) @ V.T).astype(np.float32)
+    ef = torch.empty(20, P, dtype=torch.float32, device="cuda:0")
+    ev, fve = F.fpca_eig_randomized(h, F.FPCA_F32, F.FPCA_PREC_F32, F.Grid(M), dev(torch, Gam), None, 20, 10, 2, 7,
+                                    ef)
+    om = oracle.quad_weights(M)
+    rev, rphi, rfve = oracle.eig_randomized(Gam.astype(np.float64), om, 20, 10, 2, 7)
+    assert np.abs(ev - rev).max() <= 1e-5 * rev[0]
+    assert np.abs(fve - rfve).max() <= 1e-5
+    phi = host(ef).T
+    for j in range(20):
+        gap = min(abs(rev[j] - rev[j - 1]) if j else np.inf, abs(rev[j] - rev[j + 1]) if j + 1 < 20 else np.inf)
+        scale = max(1.0, 0.1 * rev[0] / gap)
+        err = min(np.abs(phi[:, j] - rphi[:, j]).max(), np.abs(phi[:, j] + rphi[:, j]).max())
+        assert err <= 1e-3 * scale * np.abs(rphi[:, j]).max(), (j, err)
+
+
 def test_eig_degenerate_surfaces(torch, F, h):
     """A zero surface (every basis column dropped: eigenvalues, FVE and
     eigenfunctions 0) and a rank-one surface (one eigenpair, the rest 0; FVE 1)."""
