@@ -188,6 +188,14 @@ def bin_cov_identity(M, offsets, t, y, folds=None, fold_sel=-1, want_Q=False, wa
     return tuple(out)
 
 
+def bin_common_grid_mean(Y):
+    """Mean part of bin_common_grid (c = n/P, s = column sums / P), without the
+    pair sums, for sizes where the Gram product is not needed."""
+    Y = np.asarray(Y, np.float64)
+    n, P = Y.shape
+    return np.full(P, n / P), Y.sum(0) / P
+
+
 def bin_common_grid(Y):
     """Common-grid design: every curve observed at all P nodes, so each observation
     sits on a node (W = indicator). Mean: c = n/P, s = column sums / P.

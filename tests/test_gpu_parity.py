@@ -246,6 +246,32 @@ def test_smooth_mean_parity(torch, F, h, M, hb, dt):
     assert np.all(np.isnan(host(mu)[rst == 2]))
 
 
+def test_mean_common_grid_full_size(torch, F, h):
+    """Mean stage of the benchmark at its full size: common-grid binning of
+    n = 5000 curves on 64 x 64 nodes (column sums over 79 row chunks with a
+    ragged last chunk) and the smoother at h = 0.1, against the oracle."""
+    _say("mean common grid 64x64 n=5000")
+    from fpca_synth import make_c3
+    ds = make_c3(n=5000)
+    from paper_1510_04439_amd import pipeline as PL
+    dd = PL.to_device(ds)
+    P = int(np.prod(ds.M_mean))
+    c = torch.empty(P, dtype=torch.float32, device="cuda:0")
+    s = torch.empty_like(c)
+    mu = torch.empty_like(c)
+    st = torch.empty(P, dtype=torch.int8, device="cuda:0")
+    F.fpca_bin(h, dd.grid_mean, F.FPCA_BIN_MEAN, dd.design, dd.dtype, F.FPCA_PREC_F32, dd.n, None, None, dd.y,
+               None, 0, c, s)
+    F.fpca_smooth_mean(h, dd.grid_mean, dd.dtype, c, s, F.FPCA_K_EPANECHNIKOV, ds.h_mean, mu, st)
+    h.sync()
+    Y = np.asarray(ds.y, np.float64).reshape(ds.n, P)
+    rc, rs = oracle.bin_common_grid_mean(Y)
+    assert normwise_rel(host(c), rc) < 1e-7 and normwise_rel(host(s), rs) < 1e-5
+    rb, rst = oracle.smooth_mean(ds.M_mean, ds.h_mean, rc, rs)
+    assert np.array_equal(host(st), rst)
+    assert normwise_rel(host(mu), rb, rst == 0) < 1e-5
+
+
 def _cov_inputs(rng, M, d):
     """Pair weights and raw products on the 2d-grid from random curves (oracle binning)."""
     off, t, y = rand_irregular(rng, d, 60, 2, 25, np.float64)

@@ -147,6 +147,8 @@ def test_common_grid_closed_form():
     assert np.abs(G - G2).max() < 1e-14
     c, s, _, _ = oracle.bin_mean(M, off, t, Y.reshape(-1))
     assert np.abs(c - c2).max() < 1e-15 and np.abs(s - s2).max() < 1e-14
+    c3, s3 = oracle.bin_common_grid_mean(Y)
+    assert np.abs(c - c3).max() < 1e-15 and np.abs(s - s3).max() < 1e-14
     pp, qq = np.meshgrid(np.arange(P), np.arange(P), indexing="ij")
     Ge = oracle.bin_common_grid_entries(Y, pp.ravel(), qq.ravel()).reshape(P, P)
     assert np.abs(G - Ge).max() < 1e-14
