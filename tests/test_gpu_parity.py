@@ -272,6 +272,47 @@ def test_mean_common_grid_full_size(torch, F, h):
     assert normwise_rel(host(mu), rb, rst == 0) < 1e-5
 
 
+def test_end_to_end_c3_sampled(torch, F, h):
+    """The benchmark's path at full size (64 x 64 common grid, n = 5000): mean,
+    BF16x3 Gram binning and the analytic-weight covariance smoother, checked
+    at sampled covariance nodes (and their transposes) against the oracle's
+    FP64 Gram of the same data and its direct-window smoother."""
+    _say("end-to-end c3 sampled")
+    from fpca_synth import make_c3
+    from paper_1510_04439_amd import pipeline as PL
+    ds = make_c3(n=5000)
+    dd = PL.to_device(ds)
+    bufs = PL.alloc(dd, ds.k, with_status=True, analytic_C=True)
+    F.fpca_bin(h, dd.grid_mean, F.FPCA_BIN_MEAN, dd.design, dd.dtype, F.FPCA_PREC_F32, dd.n, None, None, dd.y,
+               None, 0, bufs.c, bufs.s)
+    F.fpca_smooth_mean(h, dd.grid_mean, dd.dtype, bufs.c, bufs.s, F.FPCA_K_EPANECHNIKOV, ds.h_mean, bufs.mu,
+                       bufs.mu_status)
+    F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_COV, dd.design, dd.dtype, F.FPCA_PREC_BF16X3, dd.n, None, None, dd.y,
+               None, 0, None, bufs.G)
+    F.fpca_smooth_cov(h, dd.grid_cov, dd.dtype, None, PL.uniform_pair_weight(dd), bufs.G, bufs.mu,
+                      F.FPCA_K_EPANECHNIKOV, ds.h_cov, bufs.gamma, bufs.status)
+    h.sync()
+    P = int(np.prod(ds.M_cov))
+    Y = np.asarray(ds.y, np.float64).reshape(ds.n, P)
+    rc, rs = oracle.bin_common_grid_mean(Y)
+    mu, _ = oracle.smooth_mean(ds.M_mean, ds.h_mean, rc, rs)
+    _, _, C, G = oracle.bin_common_grid(Y)
+    rng = np.random.default_rng(33)
+    idx = rng.integers(0, P * P, 300)
+    p, q = idx // P, idx % P
+    near = rng.integers(0, P, 60)  # nodes near the diagonal s = t, where the full system is solved
+    p = np.concatenate([p, near])
+    q = np.concatenate([q, np.clip(near + rng.integers(-2, 3, 60) * 64 + rng.integers(-2, 3, 60), 0, P - 1)])
+    nodes = np.concatenate([p * P + q, q * P + p])
+    rb, rst = oracle.smooth_cov_raw(ds.M_cov, ds.h_cov, C, G, nodes)
+    m = len(p)
+    ref = 0.5 * (rb[:m] + rb[m:]) - mu[p] * mu[q]
+    ok = (rst[:m] == 0) & (rst[m:] == 0)
+    gam = host(bufs.gamma)
+    assert normwise_rel(gam[p, q], ref, ok) < 1e-4
+    assert status_agreement(host(bufs.status).reshape(-1)[nodes], rst)[0] == 0
+
+
 def _cov_inputs(rng, M, d):
     """Pair weights and raw products on the 2d-grid from random curves (oracle binning)."""
     off, t, y = rand_irregular(rng, d, 60, 2, 25, np.float64)
