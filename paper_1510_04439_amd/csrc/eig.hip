@@ -463,8 +463,9 @@ __device__ inline void rr_pair(int ne, int step, int m, int *a, int *b) {
 
 // One workgroup: B = Q^T A Q on the active columns (symmetrized, placed first,
 // zero rows and columns for the rest), cyclic Jacobi with round-robin ordering
-// of all RP indices (a pair with an inactive index has a zero off-diagonal
-// and rotates by the identity). Thread (m1, m2) of the (RP/2)^2 threads owns
+// of the n active indices (rounded up to even; the inactive ones form fixed
+// pairs of zero rows and rotate by the identity). Thread (m1, m2) of the
+// (RP/2)^2 threads owns
 // the 2x2 block (pair m1) x (pair m2) of B and the entries of V in rows m1 and
 // m1 + RP/2, pair m2: it computes rotation m2 from the current B and takes
 // rotation m1 from the lane of its wave that computed it (or computes it too
@@ -514,11 +515,27 @@ __global__ __launch_bounds__((RP / 2) * (RP / 2)) void k_jacobi(const double *__
   for (int e = tid; e < RP * RP; e += NT) Bb[0][(e / RP) * LD + e % RP] = ldexp(Bb[0][(e / RP) * LD + e % RP], -ex);
   __syncthreads();
   const int m1 = tid / H, m2 = tid % H;
-  // step 0 pairs; every later step moves each index of a pair on by one
-  // (mod RP - 1), except index RP - 1 of pair 0
+  // Round robin over the ne = n + (n & 1) leading indices (pairs m < ne/2):
+  // step 0 pairs, then every step moves each index of a pair on by one
+  // (mod ne - 1), except index ne - 1 of pair 0. Pairs m >= ne/2 are the
+  // fixed inactive pairs (2m, 2m + 1) and rotate by the identity.
+  const int ne = n + (n & 1);
+  auto first_pair = [&](int m, int *a, int *b) {
+    if (m >= ne / 2) {
+      *a = 2 * m;
+      *b = 2 * m + 1;
+    } else {
+      rr_pair(ne, 0, m, a, b);
+    }
+  };
   int a1, b1, a2, b2;
-  rr_pair(RP, 0, m1, &a1, &b1);
-  rr_pair(RP, 0, m2, &a2, &b2);
+  first_pair(m1, &a1, &b1);
+  first_pair(m2, &a2, &b2);
+  auto next_pair = [&](int m, int *a, int *b) {
+    if (m >= ne / 2) return;
+    if (m != 0) *a = *a + 1 == ne - 1 ? 0 : *a + 1;
+    *b = *b + 1 == ne - 1 ? 0 : *b + 1;
+  };
   int cur = 0;
   for (int sweep = 0; sweep < 60 && n >= 2; ++sweep) {
     // convergence: sum of squares off the diagonal against the total
@@ -544,7 +561,7 @@ __global__ __launch_bounds__((RP / 2) * (RP / 2)) void k_jacobi(const double *__
       st += red_tot[sweep & 1][wv];
     }
     if (!(so > 1e-28 * st)) break;  // uniform: every thread summed the same partials
-    for (int step = 0; step < RP - 1; ++step) {
+    for (int step = 0; step < ne - 1; ++step) {
       const double *B = Bb[cur];
       double *Bn = Bb[cur ^ 1];
       // every LDS read of the step is issued before the rotation is formed
@@ -580,10 +597,8 @@ __global__ __launch_bounds__((RP / 2) * (RP / 2)) void k_jacobi(const double *__
         Vb[row * LD + a2] = c2 * va[h] - s2 * vb[h];
         Vb[row * LD + b2] = s2 * va[h] + c2 * vb[h];
       }
-      a1 = (m1 == 0) ? a1 : (a1 + 1 == RP - 1 ? 0 : a1 + 1);
-      a2 = (m2 == 0) ? a2 : (a2 + 1 == RP - 1 ? 0 : a2 + 1);
-      b1 = b1 + 1 == RP - 1 ? 0 : b1 + 1;
-      b2 = b2 + 1 == RP - 1 ? 0 : b2 + 1;
+      next_pair(m1, &a1, &b1);
+      next_pair(m2, &a2, &b2);
       __syncthreads();
       cur ^= 1;
     }
