@@ -226,26 +226,24 @@ def main():
                                                ds.oversample, ds.power_iters, ds.rp_seed, b.efuns)
         if ev: ev[4].record(torch.cuda.current_stream())
 
+    def run(nsteps):
+        """nsteps pipelined steps: step i+1's binning and smoothing are queued before step i's
+        eigendecomposition, on the other slot's handle, buffers and stream."""
+        with torch.cuda.stream(streams[0]):
+            stages(0)
+        for i in range(nsteps):
+            if i + 1 < nsteps:
+                with torch.cuda.stream(streams[(i + 1) % 2]):
+                    stages((i + 1) % 2)
+            with torch.cuda.stream(streams[i % 2]):
+                eig(i % 2)  # returns after this step's eigenvalues reached the host
+
     log("warmup")
-    for _ in range(max(args.warmup, 1)):
-        for slot in (0, 1):
-            with torch.cuda.stream(streams[slot]):
-                stages(slot)
-                eig(slot)
-    torch.cuda.synchronize()
-    log("timed steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     with torch.cuda.stream(streams[0]):
-        stages(0)
-    for i in range(args.steps):
-        if i + 1 < args.steps:
-            with torch.cuda.stream(streams[(i + 1) % 2]):
-                stages((i + 1) % 2)
-        with torch.cuda.stream(streams[i % 2]):
-            eig(i % 2)  # returns after this step's eigenvalues reached the host
+        for _ in range(max(args.warmup, 1)):
+            stages(0)
+            eig(0)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     # per-step latency and stage times: the same steps one after another on one stream
     log("sequential steps (latency and stage times)")
     nseq = min(args.steps, 10)
@@ -258,6 +256,13 @@ def main():
             eig(0, recs[i])
     torch.cuda.synchronize()
     latency_ms = (time.perf_counter() - t1) * 1e3 / nseq
+    log("timed steps")
+    run(2 * max(args.warmup, 1))  # pipelined warm-up (both slots, the streams of the pipeline)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     for hh in hs:
         hh.sync()
     stages_ = {"bin_mean+smooth_mean": [], "bin_cov": [], "smooth_cov": [], "eig": []}
@@ -295,8 +300,8 @@ def main():
                    "gram_prec": args.gram_prec},
         "stages_ms": stage_ms,
         "latency_ms_per_step": latency_ms,
-        "pipelining": "steps alternate over two handles and streams; step i+1's binning and smoothing run "
-                      "beside step i's eigendecomposition (stages_ms and latency from sequential steps)",
+        "pipelining": "steps alternate over two handles, buffer sets and streams; step i+1's binning and "
+                      "smoothing run beside step i's eigendecomposition (stages_ms and latency from sequential steps)",
         "smooth_cov_pts_per_s": nodes / (sc_ms / 1e3),
         "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (k_tables, k_stage_t, k_stage_s)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
