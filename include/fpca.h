@@ -212,6 +212,29 @@ int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid
                         int power_iters, uint64_t seed, double *evals, void *efuns, double *fve);
 
 /*
+ * fpca_noise_variance -- measurement-error variance (the estimator that
+ * follows eq. 2.5). At every node t of `grid` (P nodes):
+ *   sigma2_t[t] = b0[t] - gamma[t, t] - mu[t]^2
+ * where b0 is fpca_smooth_mean applied to the weights and sq_sums of
+ * fpca_bin(kind = MEAN) (the squared responses of eq. 2.5, curve weight
+ * 1/N_i) with the bandwidth h_sigma, mu the smoothed mean and gamma the P x P
+ * covariance of fpca_smooth_cov, all on the same grid. b0 estimates
+ * E Y^2 = mu^2 + Gamma(t,t) + sigma^2, so mu^2 is subtracted; the paper
+ * prints the product with a plus sign. Nodes outside Omega (grid mask) get 0
+ * and are not counted; a node whose value is not finite (an EMPTY window of
+ * either smoother) keeps NaN and is not counted.
+ *   sigma2: host, one double: the average of sigma2_t over the counted nodes
+ *     (the integral over Omega divided by the volume of Omega, as a node
+ *     average); NaN when no node counts.
+ *   count: host int64 (or NULL): the number of counted nodes.
+ *   b0, mu: device, P values of `dtype`; gamma: device, P x P of `dtype`;
+ *   sigma2_t: device, P values of `dtype`, or NULL. The sum is FP64 in a
+ *   fixed order. Synchronizes the handle's stream.
+ */
+int fpca_noise_variance(fpca_handle handle, const fpca_grid *grid, int dtype, const void *b0, const void *mu,
+                        const void *gamma, void *sigma2_t, double *sigma2, int64_t *count);
+
+/*
  * fpca_cv_batched -- bandwidth selection for the covariance smoother by
  * leave-curves-out cross-validation (the CV idea of Section 3.3, on folds of
  * curves and binned data). For every bandwidth h (row of `bandwidths`) and

@@ -10,6 +10,7 @@ product, a Householder QR, a symmetric eigensolver).
 Each function names the passage of the paper it follows:
   - linear binning: Section 3.2 (binning strategy for irregular designs);
   - mean smoother: eq. (2.3); covariance smoother: eq. (2.4);
+  - noise variance: the estimator after eq. (2.5);
   - matrixization and rescaling: Section 3.1, eq. (3.1);
   - random projection: Section 3.4.
 """
@@ -288,6 +289,29 @@ def assemble_cov(Ghat, mu, mask=None):
         Gam[~m, :] = 0.0
         Gam[:, ~m] = 0.0
     return 0.5 * (Gam + Gam.T)
+
+
+def noise_variance(b0, mu, gamma, mask=None):
+    """Measurement-error variance, the estimator that follows eq. (2.5).
+
+    b0 is the smooth of the squared responses Y_ij^2 with the mean's weights
+    1/N_i (eq. 2.5), which estimates E Y^2 = mu^2 + Gamma(t,t) + sigma^2; so at
+    every node sigma2(t) = b0(t) - Gamma(t,t) - mu(t)^2 (the paper prints the
+    mean product with a plus sign; the minus sign is the reading used). The
+    constant sigma^2 is the integral over Omega divided by the volume of
+    Omega, taken as the average over the grid nodes of Omega where the value is
+    finite. Nodes outside Omega get 0. Returns (sigma2_t, sigma2, count)."""
+    b0 = np.asarray(b0, np.float64).reshape(-1)
+    mu = np.asarray(mu, np.float64).reshape(-1)
+    gamma = np.asarray(gamma, np.float64)
+    P = b0.size
+    assert mu.size == P and gamma.shape == (P, P)
+    inside = np.ones(P, bool) if mask is None else np.asarray(mask).reshape(-1).astype(bool)
+    s2t = np.where(inside, (b0 - np.diag(gamma)) - mu * mu, 0.0)
+    counted = inside & np.isfinite(s2t)
+    count = int(counted.sum())
+    sigma2 = float(s2t[counted].sum() / count) if count else float("nan")
+    return s2t, sigma2, count
 
 
 # ----------------------------------------------------------------- eigen

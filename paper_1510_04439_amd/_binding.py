@@ -32,7 +32,7 @@ EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
-    "fpca_bw_mlp_backward", "fpca_bw_adam_step",
+    "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance",
 ]
 
 
@@ -62,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     L.fpca_destroy.argtypes = [vp]
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
+    L.fpca_noise_variance.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, vp,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.fpca_last_error.restype = ctypes.c_char_p
     L.fpca_bin.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i32, i32, i64, vp, vp, vp, vp, i32,
                            vp, vp, vp, vp, vp]
@@ -193,6 +195,16 @@ def fpca_eig_randomized(h: Handle, dtype: int, prec: int, grid: Grid, gamma, qua
                                               ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ev, _ptr(efuns),
                                               fv))
     return np.array(ev[:]), np.array(fv[:])
+
+
+def fpca_noise_variance(h: Handle, grid: Grid, dtype: int, b0, mu, gamma, sigma2_t=None):
+    """Returns (sigma2, count); writes the per-node values into sigma2_t when given."""
+    g = grid.c()
+    s2 = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load_library().fpca_noise_variance(h.ptr, ctypes.byref(g), int(dtype), _ptr(b0), _ptr(mu), _ptr(gamma),
+                                              _ptr(sigma2_t), ctypes.byref(s2), ctypes.byref(cnt)))
+    return s2.value, cnt.value
 
 
 def fpca_rng_normal(h: Handle, seed: int, count: int, out):

@@ -457,3 +457,69 @@ def test_features_lag_structure_and_counts():
     np.testing.assert_allclose(f[12:12 + 5], rho ** np.arange(1, 6), rtol=1e-12)
     np.testing.assert_allclose(f[20:20 + 4], rho ** np.arange(1, 5), rtol=1e-12)
     assert abs(f[9] - np.log(2.0)) < 1e-12 and abs(f[10] - (3.0 - 2.0) / 3.0) < 1e-12
+
+
+# ------------------------------------------------------------------ noise variance (after eq. 2.5)
+@pytest.mark.parametrize("M,h", [((7,), 0.4), ((3, 3), 0.8)])
+def test_noise_variance_hadamard_design(M, h):
+    """Closed form: curves Y_i = a + s r_i on a common grid, with r_i the rows of
+    a Hadamard matrix without its constant column (columns orthogonal and
+    summing to zero). Then the binned mean is a, the binned second moment
+    a^2 + s^2, the off-diagonal raw covariance a^2, so Gamma = 0 and the noise
+    variance is exactly s^2 at every node (the printed plus sign would give
+    s^2 + 2 a^2)."""
+    from scipy.linalg import hadamard
+    P = int(np.prod(M))
+    H = 1
+    while H < P + 1:
+        H *= 2
+    r = hadamard(H)[:, 1:P + 1].astype(np.float64)
+    a, sd = 0.8, 0.3
+    Y = a + sd * r
+    c, s = oracle.bin_common_grid_mean(Y)
+    _, sq = oracle.bin_common_grid_mean(Y * Y)
+    mu, st = oracle.smooth_mean(M, h, c, s)
+    b0, st2 = oracle.smooth_mean(M, h, c, sq)
+    _, _, C, G = oracle.bin_common_grid(Y)
+    Ghat, st3 = oracle.smooth_cov_raw(M, h, C, G)
+    assert np.all(st == 0) and np.all(st2 == 0) and np.all(st3 == 0)
+    gam = oracle.assemble_cov(Ghat.reshape(P, P), mu)
+    s2t, s2, cnt = oracle.noise_variance(b0, mu, gam)
+    assert cnt == P
+    assert np.abs(s2t - sd * sd).max() < 1e-12
+    assert abs(s2 - sd * sd) < 1e-12
+
+
+def test_noise_variance_linear_surfaces_and_mask():
+    """Synthesized binned arrays whose smooths are exact (local-linear
+    reproduction): mu = a, Gamma(s,t) = alpha + beta (s + t), b0(t) = a^2 +
+    alpha + 2 beta t + sigma^2. The noise variance is sigma^2 at every node,
+    which needs Gamma's diagonal (Gamma(t,0) would leave beta t). Nodes
+    outside the mask get 0 and are not counted."""
+    M = (9,)
+    P = 9
+    x = grid_points(M)[:, 0]
+    rng = np.random.default_rng(5)
+    c = rng.random(P) + 0.5
+    a, alpha, beta, sig2 = 0.6, 0.3, 0.25, 0.04
+    s = c * a
+    sq = c * (a * a + alpha + 2 * beta * x + sig2)
+    C = np.outer(c, c)
+    np.fill_diagonal(C, 0.0)
+    G = C * (a * a + alpha + beta * (x[:, None] + x[None, :]))
+    h = 0.3
+    mu, _ = oracle.smooth_mean(M, h, c, s)
+    b0, _ = oracle.smooth_mean(M, h, c, sq)
+    Ghat, st = oracle.smooth_cov_raw(M, h, C, G)
+    assert np.all(st == 0)
+    gam = oracle.assemble_cov(Ghat.reshape(P, P), mu)
+    s2t, s2, cnt = oracle.noise_variance(b0, mu, gam)
+    assert cnt == P and abs(s2 - sig2) < 1e-12 and np.abs(s2t - sig2).max() < 1e-12
+    mask = np.ones(P, np.uint8)
+    mask[[0, 4]] = 0
+    s2t, s2, cnt = oracle.noise_variance(b0, mu, gam, mask)
+    assert cnt == P - 2 and s2t[0] == 0 and s2t[4] == 0 and abs(s2 - sig2) < 1e-12
+    b0n = b0.copy()
+    b0n[2] = np.nan
+    s2t, s2, cnt = oracle.noise_variance(b0n, mu, gam)
+    assert cnt == P - 1 and np.isnan(s2t[2]) and abs(s2 - sig2) < 1e-12
