@@ -235,6 +235,31 @@ int fpca_noise_variance(fpca_handle handle, const fpca_grid *grid, int dtype, co
                         const void *gamma, void *sigma2_t, double *sigma2, int64_t *count);
 
 /*
+ * fpca_pace_scores -- principal component scores by conditional expectation
+ * (eqs. 2.6 and 2.7): for every curve i,
+ *   xi_i = Lambda Phi_i^T Sigma_i^{-1} (Y_i - mu_i),
+ *   Sigma_i = Phi_i Lambda Phi_i^T + sigma2 I,
+ * with Phi_i[j][l] = efuns_l(t_ij) and mu_i[j] = mu(t_ij) interpolated from
+ * the grid by the multilinear corner weights of linear binning (the rule of
+ * fpca_bin). Computed per curve as the k x k system
+ *   (Phi_i^T Phi_i + sigma2 Lambda^{-1}) xi_i = Phi_i^T (Y_i - mu_i)
+ * (the same result by the push-through identity), FP64 accumulation and
+ * Cholesky solve. Components with evals[l] <= 0 are left out of Sigma_i and
+ * score 0. Observations with t outside [0,1]^d, or a non-finite y, are left
+ * out; a curve with none scores 0.
+ *   design, n, offsets, t, y: as in fpca_bin (common grid: y is n x P with
+ *     NaN for a missing value, offsets = t = NULL).
+ *   mu: device, P values; efuns: device, P x k column-major (the output of
+ *     fpca_eig_randomized); evals: host, k doubles; sigma2 > 0 (for example
+ *     from fpca_noise_variance).
+ *   scores: device, n x k row-major, of `dtype`.
+ * Returns FPCA_ERR_INVALID_ARG for k outside 1..32 or sigma2 not positive.
+ */
+int fpca_pace_scores(fpca_handle handle, const fpca_grid *grid, int design, int dtype, int64_t n,
+                     const int64_t *offsets, const void *t, const void *y, const void *mu, const void *efuns,
+                     int k, const double *evals, double sigma2, void *scores);
+
+/*
  * fpca_cv_batched -- bandwidth selection for the covariance smoother by
  * leave-curves-out cross-validation (the CV idea of Section 3.3, on folds of
  * curves and binned data). For every bandwidth h (row of `bandwidths`) and

@@ -11,6 +11,7 @@ Each function names the passage of the paper it follows:
   - linear binning: Section 3.2 (binning strategy for irregular designs);
   - mean smoother: eq. (2.3); covariance smoother: eq. (2.4);
   - noise variance: the estimator after eq. (2.5);
+  - principal component scores: eqs. (2.6) and (2.7);
   - matrixization and rescaling: Section 3.1, eq. (3.1);
   - random projection: Section 3.4.
 """
@@ -312,6 +313,49 @@ def noise_variance(b0, mu, gamma, mask=None):
     count = int(counted.sum())
     sigma2 = float(s2t[counted].sum() / count) if count else float("nan")
     return s2t, sigma2, count
+
+
+def pace_scores(M, offsets, t, y, mu, efuns, evals, sigma2):
+    """Principal component scores by conditional expectation (eqs. 2.6 and 2.7),
+    solved in the N_i x N_i form as written: xi_i = Lambda Phi_i^T Sigma_i^{-1}
+    (Y_i - mu_i), Sigma_i = Phi_i Lambda Phi_i^T + sigma2 I, with phi_l and mu at
+    t_ij interpolated by the corner weights of linear binning (Section 3.2).
+    Components with evals <= 0 are left out (Lambda entry 0, score 0);
+    observations outside [0,1]^d or with a non-finite y are left out.
+    `offsets`/`t` None: common grid, y is n x P (NaN = missing).
+    Returns scores [n, k]."""
+    efuns = np.asarray(efuns, np.float64)
+    P, k = efuns.shape
+    mu = np.asarray(mu, np.float64).reshape(-1)
+    lam = np.asarray(evals, np.float64)[:k]
+    lam = np.where(np.isfinite(lam) & (lam > 0), lam, 0.0)
+    if offsets is None:
+        Y = np.asarray(y, np.float64)
+        n = Y.shape[0]
+        per_curve = [(np.arange(P)[np.isfinite(Y[i])], None, Y[i][np.isfinite(Y[i])]) for i in range(n)]
+    else:
+        d = len(M)
+        tt = np.asarray(t, np.float64).reshape(-1, d)
+        yy = np.asarray(y, np.float64).reshape(-1)
+        inside = np.all((tt >= 0) & (tt <= 1), axis=1) & np.isfinite(yy)
+        node, wt, _ = bin_corners(M, np.where(inside[:, None], tt, 0.0))
+        per_curve = []
+        for i in range(len(offsets) - 1):
+            sl = np.arange(offsets[i], offsets[i + 1])
+            sl = sl[inside[sl]]
+            per_curve.append((node[sl], wt[sl], yy[sl]))
+    out = np.zeros((len(per_curve), k))
+    for i, (nd, w, yi) in enumerate(per_curve):
+        if yi.size == 0:
+            continue
+        if w is None:
+            Phi, mui = efuns[nd], mu[nd]
+        else:
+            Phi = np.einsum("jc,jcl->jl", w, efuns[nd])
+            mui = (w * mu[nd]).sum(1)
+        Sig = (Phi * lam) @ Phi.T + sigma2 * np.eye(yi.size)
+        out[i] = lam * (Phi.T @ np.linalg.solve(Sig, yi - mui))
+    return out
 
 
 # ----------------------------------------------------------------- eigen

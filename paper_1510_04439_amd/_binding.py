@@ -32,7 +32,7 @@ EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
-    "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance",
+    "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
 ]
 
 
@@ -62,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     L.fpca_destroy.argtypes = [vp]
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
+    L.fpca_pace_scores.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, i32,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
     L.fpca_noise_variance.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, vp,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.fpca_last_error.restype = ctypes.c_char_p
@@ -205,6 +207,15 @@ def fpca_noise_variance(h: Handle, grid: Grid, dtype: int, b0, mu, gamma, sigma2
     _check(load_library().fpca_noise_variance(h.ptr, ctypes.byref(g), int(dtype), _ptr(b0), _ptr(mu), _ptr(gamma),
                                               _ptr(sigma2_t), ctypes.byref(s2), ctypes.byref(cnt)))
     return s2.value, cnt.value
+
+
+def fpca_pace_scores(h: Handle, grid: Grid, design: int, dtype: int, n: int, offsets, t, y, mu, efuns, k: int,
+                     evals, sigma2: float, scores):
+    g = grid.c()
+    ev = (ctypes.c_double * k)(*[float(v) for v in np.asarray(evals, np.float64)[:k]])
+    _check(load_library().fpca_pace_scores(h.ptr, ctypes.byref(g), int(design), int(dtype), int(n), _ptr(offsets),
+                                           _ptr(t), _ptr(y), _ptr(mu), _ptr(efuns), int(k), ev, float(sigma2),
+                                           _ptr(scores)))
 
 
 def fpca_rng_normal(h: Handle, seed: int, count: int, out):

@@ -10,6 +10,7 @@
 // Covariance, common grid: G = Y^T Y / (P(P-1)) with the diagonal removed.
 #include <cmath>
 
+#include "binrule.hpp"
 #include "common.hpp"
 
 namespace fpca {
@@ -18,37 +19,6 @@ int gram_i32(fpca_context *ctx, const int32_t *A, int64_t K, int64_t N, int64_t 
 
 namespace fpca {
 namespace {
-
-// Lower corner and fractions of one observation; false if any coordinate is
-// outside [0,1] or NaN. u = x*(M-1) is one rounded FP64 multiply (exact for
-// FP32 inputs), never fused with the subtraction that follows.
-template <typename T>
-__device__ inline bool locate(const T *x, const GridDims &g, int *k, double *rho) {
-#pragma clang fp contract(off)
-  for (int q = 0; q < g.d; ++q) {
-    double xv = double(x[q]);
-    if (!(xv >= 0.0 && xv <= 1.0)) return false;
-    double u = xv * double(g.M[q] - 1);
-    int kq = int(floor(u));
-    if (kq > g.M[q] - 2) kq = g.M[q] - 2;
-    k[q] = kq;
-    rho[q] = u - double(kq);
-  }
-  return true;
-}
-
-__device__ inline void corner(const GridDims &g, const int *k, const double *rho, int c, int64_t *p,
-                              double *W) {
-  int64_t pp = 0;
-  double w = 1.0;
-  for (int q = 0; q < g.d; ++q) {
-    int bit = (c >> (g.d - 1 - q)) & 1;
-    pp += int64_t(k[q] + bit) * g.stride[q];
-    w *= bit ? rho[q] : (1.0 - rho[q]);
-  }
-  *p = pp;
-  *W = w;
-}
 
 __device__ inline void atomic_add_t(float *p, double v) { atomicAdd(p, float(v)); }
 __device__ inline void atomic_add_t(double *p, double v) { atomicAdd(p, v); }

@@ -523,3 +523,80 @@ def test_noise_variance_linear_surfaces_and_mask():
     b0n[2] = np.nan
     s2t, s2, cnt = oracle.noise_variance(b0n, mu, gam)
     assert cnt == P - 1 and np.isnan(s2t[2]) and abs(s2 - sig2) < 1e-12
+
+
+# ------------------------------------------------------------------ PACE scores (eqs. 2.6, 2.7)
+def _pace_case(rng, M, n, k, Nlo, Nhi):
+    d = len(M)
+    P = int(np.prod(M))
+    Ni = rng.integers(Nlo, Nhi + 1, size=n)
+    off = np.concatenate([[0], np.cumsum(Ni)]).astype(np.int64)
+    t = rng.random((int(off[-1]), d))
+    efuns = rng.standard_normal((P, k))
+    mu = rng.standard_normal(P)
+    return off, t, efuns, mu
+
+
+def test_pace_noise_free_limit_recovers_scores():
+    """Curves built exactly as mu + sum_l xi_l phi_l at their points (values
+    interpolated from the grid): as sigma2 -> 0 the conditional expectation
+    tends to the least-squares coefficients, i.e. the generating xi. A missing
+    Lambda in front (or a transposed Phi) would give other values."""
+    rng = np.random.default_rng(11)
+    M, n, k = (9, 7), 6, 4
+    off, t, efuns, mu = _pace_case(rng, M, n, k, 12, 30)
+    node, wt, _ = oracle.bin_corners(M, t)
+    Phi = np.einsum("jc,jcl->jl", wt, efuns[node])
+    mut = (wt * mu[node]).sum(1)
+    xi = rng.standard_normal((n, k))
+    y = mut.copy()
+    for i in range(n):
+        sl = slice(off[i], off[i + 1])
+        y[sl] += Phi[sl] @ xi[i]
+    lam = np.array([2.0, 1.0, 0.5, 0.25])
+    got = oracle.pace_scores(M, off, t, y, mu, efuns, lam, 1e-12)
+    assert np.abs(got - xi).max() < 1e-8
+
+
+def test_pace_single_observation_closed_form():
+    """N_i = 1: xi_l = lambda_l phi_l(t) (y - mu(t)) / (sum_m lambda_m phi_m(t)^2 + sigma2);
+    a component with lambda <= 0 scores 0."""
+    rng = np.random.default_rng(12)
+    M, k = (11,), 3
+    off, t, efuns, mu = _pace_case(rng, M, 5, k, 1, 1)
+    y = rng.standard_normal(5)
+    lam = np.array([1.5, -0.2, 0.7])
+    s2 = 0.3
+    got = oracle.pace_scores(M, off, t, y, mu, efuns, lam, s2)
+    node, wt, _ = oracle.bin_corners(M, t)
+    for i in range(5):
+        ph = wt[i] @ efuns[node[i]]
+        m = wt[i] @ mu[node[i]]
+        lp = np.array([1.5, 0.0, 0.7])
+        ref = lp * ph * (y[i] - m) / ((lp * ph * ph).sum() + s2)
+        assert np.abs(got[i] - ref).max() < 1e-13
+    assert np.all(got[:, 1] == 0)
+
+
+def test_pace_common_grid_missing_values():
+    """Common grid with NaN entries: those observations are left out, which
+    equals the irregular design over the observed nodes; a curve with no
+    observation scores 0."""
+    rng = np.random.default_rng(13)
+    M, n, k = (5, 4), 4, 3
+    P = 20
+    efuns = rng.standard_normal((P, k))
+    mu = rng.standard_normal(P)
+    Y = rng.standard_normal((n, P))
+    Y[rng.random((n, P)) < 0.3] = np.nan
+    Y[3] = np.nan
+    lam = np.array([1.0, 0.5, 0.2])
+    got = oracle.pace_scores(M, None, None, Y, mu, efuns, lam, 0.1)
+    pts = grid_points(M)
+    obs = [np.nonzero(np.isfinite(Y[i]))[0] for i in range(n)]
+    off = np.concatenate([[0], np.cumsum([o.size for o in obs])]).astype(np.int64)
+    t = np.concatenate([pts[o] for o in obs])
+    y = np.concatenate([Y[i][o] for i, o in enumerate(obs)])
+    ref = oracle.pace_scores(M, off, t, y, mu, efuns, lam, 0.1)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.all(got[3] == 0)
