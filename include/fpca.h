@@ -212,8 +212,8 @@ int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid
                         int power_iters, uint64_t seed, double *evals, void *efuns, double *fve);
 
 /*
- * fpca_noise_variance -- measurement-error variance (the estimator that
- * follows eq. 2.5). At every node t of `grid` (P nodes):
+ * fpca_noise_variance -- measurement-error variance (eq. 2.6, from the
+ * smooth of eq. 2.5). At every node t of `grid` (P nodes):
  *   sigma2_t[t] = b0[t] - gamma[t, t] - mu[t]^2
  * where b0 is fpca_smooth_mean applied to the weights and sq_sums of
  * fpca_bin(kind = MEAN) (the squared responses of eq. 2.5, curve weight
@@ -236,7 +236,7 @@ int fpca_noise_variance(fpca_handle handle, const fpca_grid *grid, int dtype, co
 
 /*
  * fpca_pace_scores -- principal component scores by conditional expectation
- * (eqs. 2.6 and 2.7): for every curve i,
+ * (eq. 2.7): for every curve i,
  *   xi_i = Lambda Phi_i^T Sigma_i^{-1} (Y_i - mu_i),
  *   Sigma_i = Phi_i Lambda Phi_i^T + sigma2 I,
  * with Phi_i[j][l] = efuns_l(t_ij) and mu_i[j] = mu(t_ij) interpolated from
@@ -258,6 +258,16 @@ int fpca_noise_variance(fpca_handle handle, const fpca_grid *grid, int dtype, co
 int fpca_pace_scores(fpca_handle handle, const fpca_grid *grid, int design, int dtype, int64_t n,
                      const int64_t *offsets, const void *t, const void *y, const void *mu, const void *efuns,
                      int k, const double *evals, double sigma2, void *scores);
+
+/*
+ * fpca_reconstruct -- curves on the grid from their scores (the display after
+ * eq. 2.7): xhat[i][p] = mu[p] + sum_{l < k} scores[i][l] efuns_l[p].
+ *   mu: device, P; efuns: device, P x k column-major; scores: device, n x k
+ *   row-major (fpca_pace_scores); xhat: device, n x P row-major; all of
+ *   `dtype`, FP64 accumulation. k in 1..32.
+ */
+int fpca_reconstruct(fpca_handle handle, int dtype, int64_t P, int64_t n, int k, const void *mu,
+                     const void *efuns, const void *scores, void *xhat);
 
 /*
  * fpca_cv_batched -- bandwidth selection for the covariance smoother by

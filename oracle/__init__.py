@@ -10,8 +10,8 @@ product, a Householder QR, a symmetric eigensolver).
 Each function names the passage of the paper it follows:
   - linear binning: Section 3.2 (binning strategy for irregular designs);
   - mean smoother: eq. (2.3); covariance smoother: eq. (2.4);
-  - noise variance: the estimator after eq. (2.5);
-  - principal component scores: eqs. (2.6) and (2.7);
+  - noise variance: eq. (2.6), from the smooth of eq. (2.5);
+  - principal component scores: eq. (2.7); reconstruction after it;
   - matrixization and rescaling: Section 3.1, eq. (3.1);
   - random projection: Section 3.4.
 """
@@ -293,7 +293,7 @@ def assemble_cov(Ghat, mu, mask=None):
 
 
 def noise_variance(b0, mu, gamma, mask=None):
-    """Measurement-error variance, the estimator that follows eq. (2.5).
+    """Measurement-error variance, eq. (2.6), from the smooth of eq. (2.5).
 
     b0 is the smooth of the squared responses Y_ij^2 with the mean's weights
     1/N_i (eq. 2.5), which estimates E Y^2 = mu^2 + Gamma(t,t) + sigma^2; so at
@@ -316,7 +316,7 @@ def noise_variance(b0, mu, gamma, mask=None):
 
 
 def pace_scores(M, offsets, t, y, mu, efuns, evals, sigma2):
-    """Principal component scores by conditional expectation (eqs. 2.6 and 2.7),
+    """Principal component scores by conditional expectation (eq. 2.7),
     solved in the N_i x N_i form as written: xi_i = Lambda Phi_i^T Sigma_i^{-1}
     (Y_i - mu_i), Sigma_i = Phi_i Lambda Phi_i^T + sigma2 I, with phi_l and mu at
     t_ij interpolated by the corner weights of linear binning (Section 3.2).
@@ -356,6 +356,12 @@ def pace_scores(M, offsets, t, y, mu, efuns, evals, sigma2):
         Sig = (Phi * lam) @ Phi.T + sigma2 * np.eye(yi.size)
         out[i] = lam * (Phi.T @ np.linalg.solve(Sig, yi - mui))
     return out
+
+
+def reconstruct(mu, efuns, scores):
+    """Curves on the grid from their scores (the display after eq. 2.7):
+    X_i(t) = mu(t) + sum_l xi_il phi_l(t). Returns [n, P]."""
+    return np.asarray(mu, np.float64)[None, :] + np.asarray(scores, np.float64) @ np.asarray(efuns, np.float64).T
 
 
 # ----------------------------------------------------------------- eigen

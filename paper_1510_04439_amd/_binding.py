@@ -33,6 +33,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
+    "fpca_reconstruct",
 ]
 
 
@@ -62,6 +63,7 @@ def load_library(path: str = LIB_PATH):
     L.fpca_destroy.argtypes = [vp]
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
+    L.fpca_reconstruct.argtypes = [vp, i32, i64, i64, i32, vp, vp, vp, vp]
     L.fpca_pace_scores.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
     L.fpca_noise_variance.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, vp,
@@ -216,6 +218,11 @@ def fpca_pace_scores(h: Handle, grid: Grid, design: int, dtype: int, n: int, off
     _check(load_library().fpca_pace_scores(h.ptr, ctypes.byref(g), int(design), int(dtype), int(n), _ptr(offsets),
                                            _ptr(t), _ptr(y), _ptr(mu), _ptr(efuns), int(k), ev, float(sigma2),
                                            _ptr(scores)))
+
+
+def fpca_reconstruct(h: Handle, dtype: int, P: int, n: int, k: int, mu, efuns, scores, xhat):
+    _check(load_library().fpca_reconstruct(h.ptr, int(dtype), int(P), int(n), int(k), _ptr(mu), _ptr(efuns),
+                                           _ptr(scores), _ptr(xhat)))
 
 
 def fpca_rng_normal(h: Handle, seed: int, count: int, out):

@@ -1,5 +1,5 @@
-// Noise variance from the smoothed second moment of the responses (the
-// estimator that follows eq. 2.5). At each grid node t:
+// Noise variance (eq. 2.6) from the smoothed second moment of the responses
+// (eq. 2.5). At each grid node t:
 //   sigma2(t) = b0(t) - Gamma(t, t) - mu(t)^2,
 // with b0 the local-linear smooth of the binned squares Y_ij^2 under the
 // mean's curve weights 1/N_i (eq. 2.5), Gamma the assembled covariance and mu

@@ -1,5 +1,5 @@
-// Principal component scores by conditional expectation (PACE, eqs. 2.6 and
-// 2.7): for curve i,
+// Principal component scores by conditional expectation (PACE, eq. 2.7):
+// for curve i,
 //   xi_i = Lambda Phi_i^T Sigma_i^{-1} (Y_i - mu_i),
 //   Sigma_i = Phi_i Lambda Phi_i^T + sigma^2 I,
 // with Phi_i[j][l] = phi_l(t_ij) and mu_i[j] = mu(t_ij) interpolated from the
@@ -169,6 +169,48 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
   return FPCA_OK;
 }
 
+// Reconstruction on the grid (the display after eq. 2.7):
+//   xhat[i][p] = mu[p] + sum_l xi[i][l] phi_l[p].
+// Thread per node p of a 256-node block with its k basis values in registers;
+// the block's RC_CURVES score rows in LDS; writes are contiguous along p.
+constexpr int RC_CURVES = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reconstruct(int64_t P, int64_t n, int k, const T *__restrict__ mu,
+                                                     const T *__restrict__ efuns, const T *__restrict__ xi,
+                                                     T *__restrict__ xhat) {
+  __shared__ double xs[RC_CURVES][PACE_KMAX];
+  const int64_t i0 = int64_t(blockIdx.y) * RC_CURVES;
+  const int nc = int(min(int64_t(RC_CURVES), n - i0));
+  for (int e = threadIdx.x; e < nc * k; e += blockDim.x) xs[e / k][e % k] = double(xi[(i0 + e / k) * k + e % k]);
+  __syncthreads();
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double ph[PACE_KMAX];
+#pragma unroll
+  for (int l = 0; l < PACE_KMAX; ++l) ph[l] = l < k ? double(efuns[int64_t(l) * P + p]) : 0.0;
+  const double m = double(mu[p]);
+  for (int c = 0; c < nc; ++c) {
+    double v = m;
+#pragma unroll
+    for (int l = 0; l < PACE_KMAX; ++l)
+      if (l < k) v += xs[c][l] * ph[l];
+    xhat[(i0 + c) * P + p] = T(v);
+  }
+}
+
+template <typename T>
+int reconstruct_impl(fpca_context *ctx, int64_t P, int64_t n, int k, const T *mu, const T *efuns, const T *xi,
+                     T *xhat) {
+  if (n == 0 || P == 0) return FPCA_OK;
+  const int64_t gy = (n + RC_CURVES - 1) / RC_CURVES;
+  if (gy > 65535) return set_error(FPCA_ERR_UNSUPPORTED, "n = %lld curves exceeds %d", (long long)n, 65535 * RC_CURVES);
+  hipLaunchKernelGGL(k_reconstruct<T>, dim3(unsigned((P + 255) / 256), unsigned(gy)), dim3(256), 0, ctx->stream, P,
+                     n, k, mu, efuns, xi, xhat);
+  FPCA_LAUNCH_CHECK("reconstruct");
+  return FPCA_OK;
+}
+
 }  // namespace
 
 }  // namespace fpca
@@ -206,4 +248,20 @@ extern "C" int fpca_pace_scores(fpca_handle ctx, const fpca_grid *grid, int desi
   return pace_impl<float>(ctx, grid, design, n, offsets, static_cast<const float *>(t), static_cast<const float *>(y),
                           static_cast<const float *>(mu), static_cast<const float *>(efuns), k, dg,
                           static_cast<float *>(scores));
+}
+
+extern "C" int fpca_reconstruct(fpca_handle ctx, int dtype, int64_t P, int64_t n, int k, const void *mu,
+                                const void *efuns, const void *scores, void *xhat) {
+  if (int rc = check_handle(ctx)) return rc;
+  if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (P < 0 || n < 0) return set_error(FPCA_ERR_INVALID_ARG, "P and n must be >= 0");
+  if (k < 1 || k > PACE_KMAX) return set_error(FPCA_ERR_INVALID_ARG, "k = %d must be in 1..%d", k, PACE_KMAX);
+  if ((n > 0 && P > 0) && (!mu || !efuns || !scores || !xhat))
+    return set_error(FPCA_ERR_INVALID_ARG, "mu, efuns, scores and xhat are required");
+  if (int rc = set_device(ctx)) return rc;
+  if (dtype == FPCA_F64)
+    return reconstruct_impl<double>(ctx, P, n, k, static_cast<const double *>(mu), static_cast<const double *>(efuns),
+                                    static_cast<const double *>(scores), static_cast<double *>(xhat));
+  return reconstruct_impl<float>(ctx, P, n, k, static_cast<const float *>(mu), static_cast<const float *>(efuns),
+                                 static_cast<const float *>(scores), static_cast<float *>(xhat));
 }

@@ -1,4 +1,4 @@
-"""GPU parity of the noise-variance estimator (after eq. 2.5) against the oracle.
+"""GPU parity of the noise-variance estimator (eq. 2.6) against the oracle.
 
 Bars: FP64 inputs to 1e-12 (the same FP64 formula, summed in another order);
 FP32 inputs: per-node values within the FP32 rounding of the output, the

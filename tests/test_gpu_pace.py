@@ -1,4 +1,4 @@
-"""GPU parity of the PACE scores (eqs. 2.6, 2.7) against the oracle.
+"""GPU parity of the PACE scores (eq. 2.7) against the oracle.
 
 The oracle solves the N_i x N_i system as the equations write it; the HIP
 kernel solves the equivalent k x k system. Bars: FP64 1e-10 and FP32 storage
@@ -118,3 +118,83 @@ def test_pace_argument_errors(torch, F, h):
         with pytest.raises(F.FpcaError):
             F.fpca_pace_scores(h, F.Grid(M), F.FPCA_COMMON_GRID, F.FPCA_F64, 2, None, None, y, mu, ef, k,
                                np.ones(k), s2, out)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("P,n,k", [(300, 37, 7), (4096, 50, 20), (17, 1, 32)])
+def test_reconstruct_parity(torch, F, h, dt, P, n, k):
+    _say(f"reconstruct P={P} n={n} k={k} {dt}")
+    rng = np.random.default_rng(P + n + k)
+    npdt = np.float64 if dt == "f64" else np.float32
+    mu = rng.standard_normal(P).astype(npdt)
+    ef = rng.standard_normal((P, k)).astype(npdt)
+    sc = rng.standard_normal((n, k)).astype(npdt)
+    out = torch.empty(n * P, dtype=torch.float64 if dt == "f64" else torch.float32, device="cuda:0")
+    F.fpca_reconstruct(h, F.FPCA_F64 if dt == "f64" else F.FPCA_F32, P, n, k, dev(torch, mu),
+                       dev(torch, np.ascontiguousarray(ef.T)), dev(torch, sc), out)
+    h.sync()
+    got = out.cpu().numpy().astype(np.float64).reshape(n, P)
+    ref = oracle.reconstruct(mu.astype(np.float64), ef.astype(np.float64), sc.astype(np.float64))
+    tol = 1e-13 if dt == "f64" else 1e-6
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_scores_and_reconstruction_end_to_end_c1(torch, F, h):
+    """d = 1 FP64 workload on the 51-node grid, all on the GPU: binning, mean
+    and second-moment smooths, covariance, randomized eigendecomposition,
+    noise variance, PACE scores and reconstruction, against the oracle's
+    chain. Then, statistically (not parity), the reconstruction is closer to
+    the noisy observations' curves than the mean alone."""
+    _say("scores and reconstruction end-to-end c1")
+    from fpca_synth import make_c1
+    ds = make_c1()
+    M = ds.M_cov
+    P = int(np.prod(M))
+    grid = F.Grid(M)
+    n, k, hs = ds.n, ds.k, 0.04
+    off, t, y = dev(torch, ds.offsets), dev(torch, ds.t), dev(torch, ds.y)
+    f64 = torch.float64
+    c = torch.empty(P, dtype=f64, device="cuda:0")
+    s, sq, mu, b0 = (torch.empty_like(c) for _ in range(4))
+    F.fpca_bin(h, grid, F.FPCA_BIN_MEAN, F.FPCA_IRREGULAR, F.FPCA_F64, F.FPCA_PREC_F64, n, off, t, y, None, 0,
+               c, s, sq)
+    F.fpca_smooth_mean(h, grid, F.FPCA_F64, c, s, F.FPCA_K_EPANECHNIKOV, hs, mu)
+    F.fpca_smooth_mean(h, grid, F.FPCA_F64, c, sq, F.FPCA_K_EPANECHNIKOV, hs, b0)
+    C = torch.empty(P * P, dtype=f64, device="cuda:0")
+    G, gam = torch.empty_like(C), torch.empty_like(C)
+    F.fpca_bin(h, grid, F.FPCA_BIN_COV, F.FPCA_IRREGULAR, F.FPCA_F64, F.FPCA_PREC_F64, n, off, t, y, None, 0, C, G)
+    F.fpca_smooth_cov(h, grid, F.FPCA_F64, C, 0.0, G, mu, F.FPCA_K_EPANECHNIKOV, hs, gam)
+    ef = torch.empty(k * P, dtype=f64, device="cuda:0")
+    ev, _ = F.fpca_eig_randomized(h, F.FPCA_F64, F.FPCA_PREC_F64, grid, gam, None, k, ds.oversample,
+                                  ds.power_iters, ds.rp_seed, ef)
+    s2, _ = F.fpca_noise_variance(h, grid, F.FPCA_F64, b0, mu, gam, None)
+    sc = torch.empty(n * k, dtype=f64, device="cuda:0")
+    F.fpca_pace_scores(h, grid, F.FPCA_IRREGULAR, F.FPCA_F64, n, off, t, y, mu, ef, k, ev, s2, sc)
+    xh = torch.empty(n * P, dtype=f64, device="cuda:0")
+    F.fpca_reconstruct(h, F.FPCA_F64, P, n, k, mu, ef, sc, xh)
+    h.sync()
+
+    rc, rs, _, _ = oracle.bin_mean(M, ds.offsets, ds.t, ds.y)
+    _, rsq, _, _ = oracle.bin_mean(M, ds.offsets, ds.t, np.asarray(ds.y, np.float64) ** 2)
+    rmu, _ = oracle.smooth_mean(M, hs, rc, rs)
+    rb0, _ = oracle.smooth_mean(M, hs, rc, rsq)
+    rC, rG = oracle.bin_cov_pairs(M, ds.offsets, ds.t, ds.y)
+    gh, _ = oracle.smooth_cov_raw(M, hs, rC, rG)
+    rgam = oracle.assemble_cov(gh.reshape(P, P), rmu)
+    rev, rphi, _ = oracle.eig_randomized(rgam, oracle.quad_weights(M), k, ds.oversample, ds.power_iters,
+                                         ds.rp_seed)
+    _, rs2, _ = oracle.noise_variance(rb0, rmu, rgam)
+    rsc = oracle.pace_scores(M, ds.offsets, ds.t, ds.y, rmu, rphi, rev, rs2)
+    rxh = oracle.reconstruct(rmu, rphi, rsc)
+    assert abs(s2 - rs2) < 1e-9 * abs(rs2)
+    got_sc = sc.cpu().numpy().reshape(n, k)
+    assert np.abs(got_sc - rsc).max() < 1e-7 * np.abs(rsc).max()
+    got_xh = xh.cpu().numpy().reshape(n, P)
+    assert np.abs(got_xh - rxh).max() < 1e-7 * np.abs(rxh).max()
+    # statistical: at the observation points, the reconstruction explains
+    # more of the data than the mean does
+    node, wt, _ = oracle.bin_corners(M, ds.t)
+    curve = np.repeat(np.arange(n), np.diff(ds.offsets))
+    fit = (wt * got_xh[curve[:, None], node]).sum(1)
+    base = (wt * rmu[node]).sum(1)
+    assert np.mean((ds.y - fit) ** 2) < 0.5 * np.mean((ds.y - base) ** 2)

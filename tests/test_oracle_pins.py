@@ -459,7 +459,7 @@ def test_features_lag_structure_and_counts():
     assert abs(f[9] - np.log(2.0)) < 1e-12 and abs(f[10] - (3.0 - 2.0) / 3.0) < 1e-12
 
 
-# ------------------------------------------------------------------ noise variance (after eq. 2.5)
+# ------------------------------------------------------------------ noise variance (eq. 2.6)
 @pytest.mark.parametrize("M,h", [((7,), 0.4), ((3, 3), 0.8)])
 def test_noise_variance_hadamard_design(M, h):
     """Closed form: curves Y_i = a + s r_i on a common grid, with r_i the rows of
@@ -525,7 +525,7 @@ def test_noise_variance_linear_surfaces_and_mask():
     assert cnt == P - 1 and np.isnan(s2t[2]) and abs(s2 - sig2) < 1e-12
 
 
-# ------------------------------------------------------------------ PACE scores (eqs. 2.6, 2.7)
+# ------------------------------------------------------------------ PACE scores (eq. 2.7)
 def _pace_case(rng, M, n, k, Nlo, Nhi):
     d = len(M)
     P = int(np.prod(M))
@@ -600,3 +600,20 @@ def test_pace_common_grid_missing_values():
     ref = oracle.pace_scores(M, off, t, y, mu, efuns, lam, 0.1)
     assert np.abs(got - ref).max() < 1e-12
     assert np.all(got[3] == 0)
+
+
+def test_reconstruction_of_noise_free_curves():
+    """Common-grid curves mu + sum_l xi_l phi_l observed at every node: PACE in
+    the noise-free limit returns xi, and the reconstruction (the display after
+    eq. 2.7) returns the curves themselves."""
+    rng = np.random.default_rng(14)
+    M, n, k = (6, 5), 7, 4
+    P = 30
+    efuns = rng.standard_normal((P, k))
+    mu = rng.standard_normal(P)
+    xi = rng.standard_normal((n, k))
+    X = mu[None, :] + xi @ efuns.T
+    sc = oracle.pace_scores(M, None, None, X, mu, efuns, np.array([3.0, 2.0, 1.0, 0.5]), 1e-12)
+    assert np.abs(sc - xi).max() < 1e-8
+    Xh = oracle.reconstruct(mu, efuns, sc)
+    assert Xh.shape == (n, P) and np.abs(Xh - X).max() < 1e-8
