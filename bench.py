@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFS = 2500.0  # dense BF16 matrix peak of one MI355X
+FP64_PEAK_TFS = 78.6  # FP64 vector peak of one MI355X
 
 
 def log(msg):
@@ -153,6 +154,53 @@ def cv_d3_timing(h, torch, F):
             "node_solves_per_s": sc.size * P * P / t_cv}
 
 
+def f1_timing(h, torch, F, dd, ds, b):
+    """Noise variance (eq. 2.6), PACE scores (eq. 2.7) and the reconstruction on
+    the grid for the benchmark workload, from one step's smoothed mean,
+    covariance and eigenpairs (not part of the timed step)."""
+    log("noise variance, PACE scores and reconstruction")
+    P, n, k = dd.grid_cov.P, dd.n, ds.k
+    z = lambda *sh: torch.empty(*sh, dtype=dd.tdtype, device="cuda:0")
+    c2, s2, sq, b0 = z(P), z(P), z(P), z(P)
+    scores, xhat = z(n * k), z(n * P)
+    res = {}
+
+    def legs(ev=None):
+        cur = torch.cuda.current_stream()
+        if ev: ev[0].record(cur)
+        F.fpca_bin(h, dd.grid_cov, F.FPCA_BIN_MEAN, dd.design, dd.dtype, F.FPCA_PREC_F32, n, None, None, dd.y,
+                   None, 0, c2, s2, sq)
+        F.fpca_smooth_mean(h, dd.grid_cov, dd.dtype, c2, sq, F.FPCA_K_EPANECHNIKOV, ds.h_mean, b0)
+        if ev: ev[1].record(cur)
+        res["sigma2"], _ = F.fpca_noise_variance(h, dd.grid_cov, dd.dtype, b0, b.mu, b.gamma, None)
+        if ev: ev[2].record(cur)
+        F.fpca_pace_scores(h, dd.grid_cov, F.FPCA_COMMON_GRID, dd.dtype, n, None, None, dd.y, b.mu, b.efuns, k,
+                           b.evals, res["sigma2"], scores)
+        if ev: ev[3].record(cur)
+        F.fpca_reconstruct(h, dd.dtype, P, n, k, b.mu, b.efuns, scores, xhat)
+        if ev: ev[4].record(cur)
+
+    legs()
+    reps = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(3)]
+    for ev in reps:
+        legs(ev)
+    torch.cuda.synchronize()
+    med = lambda a, c: float(np.median([ev[a].elapsed_time(ev[c]) for ev in reps]))
+    rc_ms = med(3, 4)
+    rc_bytes = 4.0 * (n * P + P * (k + 1) + n * k)
+    pace_ms = med(2, 3)
+    pace_flop = 2.0 * n * P * (k * (k + 1) / 2 + k)  # upper triangle of Phi^T Phi and Phi^T (Y - mu), FP64
+    return {"sigma2": res["sigma2"], "k": k,
+            "ms": {"bin_sq+smooth_b0": med(0, 1), "noise_variance": med(1, 2), "pace_scores": pace_ms,
+                   "reconstruct": rc_ms},
+            "pace_roofline": {"bound": "alu", "alg_flop": pace_flop, "achieved": pace_flop / (pace_ms / 1e3) / 1e12,
+                              "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                              "frac": pace_flop / (pace_ms / 1e3) / 1e12 / FP64_PEAK_TFS},
+            "reconstruct_roofline": {"bound": "hbm", "alg_bytes": rc_bytes,
+                                     "achieved": rc_bytes / (rc_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": rc_bytes / (rc_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +210,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
     ap.add_argument("--no-hselect", action="store_true", help="skip the surrogate-versus-CV timing")
+    ap.add_argument("--no-f1", action="store_true", help="skip the noise-variance, PACE and reconstruction timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
@@ -312,6 +361,7 @@ def main():
                           "alg_flops": gram_flops, "mfma_flops": 3 * gram_flops * (Pc + 128) / (2 * Pc)},
         "evals_top3": [float(v) for v in bufs.evals[:3]],
     }
+    out["f1"] = None if args.no_f1 else f1_timing(h, torch, F, dd, ds, bufs)
     out["hselect"] = None if args.no_hselect else hselect_timing(h, torch)
     if not args.no_cv_d3:
         out["cv_d3"] = cv_d3_timing(h, torch, F)

@@ -19,7 +19,8 @@ namespace {
 constexpr int PACE_KMAX = 32;
 constexpr int PACE_CH = 64;  // observations staged in LDS per chunk
 constexpr int PACE_THREADS = 256;
-constexpr int PACE_ACC = (PACE_KMAX * PACE_KMAX + PACE_KMAX + PACE_THREADS - 1) / PACE_THREADS;
+constexpr int PACE_TRI = PACE_KMAX * (PACE_KMAX + 1) / 2;
+constexpr int PACE_ACC = (PACE_TRI + PACE_KMAX + PACE_THREADS - 1) / PACE_THREADS;
 
 // sigma^2 / lambda_l for the kept components, -1 for the others
 struct PaceDiag {
@@ -28,8 +29,9 @@ struct PaceDiag {
 
 // One workgroup per curve (grid-stride). Chunks of observations: each thread
 // of the first PACE_CH interpolates one observation (every component and the
-// mean), then thread e accumulates entries e, e + 256, ... of the k x k matrix
-// Phi^T Phi followed by the k entries of Phi^T (Y - mu), in observation order.
+// mean), then thread e accumulates entries e, e + 256, ... of the upper
+// triangle of Phi^T Phi (row by row) followed by the k entries of
+// Phi^T (Y - mu), in observation order.
 // Thread 0 solves the k x k system by Cholesky in FP64.
 template <typename T>
 __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, int design,
@@ -41,9 +43,17 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
   __shared__ double yc[PACE_CH];
   __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
   __shared__ double rhs[PACE_KMAX];
+  __shared__ unsigned char tri_r[PACE_TRI], tri_c[PACE_TRI];
   const int tid = threadIdx.x;
   const int64_t P = g.P;
-  const int nmat = k * k, nacc = k * k + k;
+  const int nmat = k * (k + 1) / 2, nacc = nmat + k;
+  if (tid == 0)
+    for (int r = 0, e = 0; r < k; ++r)
+      for (int c = r; c < k; ++c, ++e) {
+        tri_r[e] = (unsigned char)r;
+        tri_c[e] = (unsigned char)c;
+      }
+  __syncthreads();
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     int64_t a, b;
     if (design == FPCA_IRREGULAR) {
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
       for (int q = 0; q < PACE_ACC; ++q) {
         const int e = tid + PACE_THREADS * q;
         if (e < nmat) {
-          const int r = e / k, c = e % k;
+          const int r = tri_r[e], c = tri_c[e];
           double s = 0.0;
           for (int o = 0; o < m; ++o) s += ph[o][r] * ph[o][c];
           acc[q] += s;
@@ -113,10 +123,12 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
     for (int q = 0; q < PACE_ACC; ++q) {
       const int e = tid + PACE_THREADS * q;
       if (e < nmat) {
-        const int r = e / k, c = e % k;
+        const int r = tri_r[e], c = tri_c[e];
         const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
         // dropped components: identity rows and columns, zero right-hand side
-        A[r][c] = (kr && kc) ? acc[q] + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
+        const double v = (kr && kc) ? acc[q] + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
+        A[r][c] = v;
+        A[c][r] = v;
       } else if (e < nacc) {
         const int r = e - nmat;
         rhs[r] = dg.v[r] >= 0.0 ? acc[q] : 0.0;
