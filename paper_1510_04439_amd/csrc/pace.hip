@@ -27,19 +27,115 @@ struct PaceDiag {
   double v[PACE_KMAX];
 };
 
+// A = L L^T in place (lower triangle of A, k x k, row stride PACE_KMAX + 1);
+// false if a pivot is not positive.
+__device__ inline bool chol_inplace(double (*A)[PACE_KMAX + 1], int k) {
+  for (int c = 0; c < k; ++c) {
+    double d = A[c][c];
+    for (int p = 0; p < c; ++p) d -= A[c][p] * A[c][p];
+    if (!(d > 0.0)) return false;
+    const double lc = sqrt(d);
+    A[c][c] = lc;
+    for (int r = c + 1; r < k; ++r) {
+      double s = A[r][c];
+      for (int p = 0; p < c; ++p) s -= A[r][p] * A[c][p];
+      A[r][c] = s / lc;
+    }
+  }
+  return true;
+}
+
+// x = (L L^T)^{-1} x with L from chol_inplace.
+__device__ inline void chol_solve(const double (*L)[PACE_KMAX + 1], double *x, int k) {
+  for (int r = 0; r < k; ++r) {
+    double s = x[r];
+    for (int p = 0; p < r; ++p) s -= L[r][p] * x[p];
+    x[r] = s / L[r][r];
+  }
+  for (int r = k - 1; r >= 0; --r) {
+    double s = x[r];
+    for (int p = r + 1; p < k; ++p) s -= L[p][r] * x[p];
+    x[r] = s / L[r][r];
+  }
+}
+
+// Common grid: the factor of Phi^T Phi + sigma^2 Lambda^{-1} over all P nodes,
+// shared by every curve observed at all of them. One workgroup: the basis in
+// chunks of 64 nodes through LDS, thread e accumulates upper-triangle entry e
+// in node order; thread 0 factors. ok[0] = 1 on success.
+template <typename T>
+__global__ __launch_bounds__(PACE_THREADS) void k_pace_cg_prep(int64_t P, const T *__restrict__ efuns, int k,
+                                                               PaceDiag dg, double *__restrict__ Lout,
+                                                               int *__restrict__ ok) {
+  __shared__ double ph[PACE_CH][PACE_KMAX + 1];
+  __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
+  __shared__ unsigned char tri_r[PACE_TRI], tri_c[PACE_TRI];
+  const int tid = threadIdx.x;
+  const int nmat = k * (k + 1) / 2;
+  if (tid == 0)
+    for (int r = 0, e = 0; r < k; ++r)
+      for (int c = r; c < k; ++c, ++e) {
+        tri_r[e] = (unsigned char)r;
+        tri_c[e] = (unsigned char)c;
+      }
+  double acc[PACE_ACC];
+#pragma unroll
+  for (int q = 0; q < PACE_ACC; ++q) acc[q] = 0.0;
+  for (int64_t c0 = 0; c0 < P; c0 += PACE_CH) {
+    const int m = int(min(int64_t(PACE_CH), P - c0));
+    __syncthreads();
+    if (tid < m)
+      for (int l = 0; l < k; ++l) ph[tid][l] = double(efuns[int64_t(l) * P + c0 + tid]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PACE_ACC; ++q) {
+      const int e = tid + PACE_THREADS * q;
+      if (e < nmat) {
+        const int r = tri_r[e], c = tri_c[e];
+        double sum = 0.0;
+        for (int o = 0; o < m; ++o) sum += ph[o][r] * ph[o][c];
+        acc[q] += sum;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PACE_ACC; ++q) {
+    const int e = tid + PACE_THREADS * q;
+    if (e < nmat) {
+      const int r = tri_r[e], c = tri_c[e];
+      const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
+      const double v = (kr && kc) ? acc[q] + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
+      A[r][c] = v;
+      A[c][r] = v;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const bool good = chol_inplace(A, k);
+    for (int r = 0; r < k; ++r)
+      for (int c = 0; c < k; ++c) Lout[r * k + c] = A[r][c];
+    ok[0] = good ? 1 : 0;
+  }
+}
+
 // One workgroup per curve (grid-stride). Chunks of observations: each thread
 // of the first PACE_CH interpolates one observation (every component and the
 // mean), then thread e accumulates entries e, e + 256, ... of the upper
 // triangle of Phi^T Phi (row by row) followed by the k entries of
 // Phi^T (Y - mu), in observation order.
-// Thread 0 solves the k x k system by Cholesky in FP64.
+// Thread 0 solves the k x k system by Cholesky in FP64. On the common grid a
+// curve with no missing value takes the factor shared by all such curves.
 template <typename T>
 __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, int design,
                                                        const int64_t *__restrict__ off, const T *__restrict__ t,
                                                        const T *__restrict__ y, const T *__restrict__ mu,
                                                        const T *__restrict__ efuns, int k, PaceDiag dg,
+                                                       const double *__restrict__ Lcg, const int *__restrict__ cg_ok,
                                                        T *__restrict__ scores) {
   __shared__ double ph[PACE_CH][PACE_KMAX + 1];
+  __shared__ double Lc[PACE_KMAX][PACE_KMAX + 1];
+  __shared__ double red[PACE_THREADS / 64][PACE_KMAX];
   __shared__ double yc[PACE_CH];
   __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
   __shared__ double rhs[PACE_KMAX];
@@ -53,6 +149,9 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
         tri_r[e] = (unsigned char)r;
         tri_c[e] = (unsigned char)c;
       }
+  const bool fast = design == FPCA_COMMON_GRID && Lcg && cg_ok && cg_ok[0] == 1;
+  if (fast)
+    for (int e = tid; e < k * k; e += PACE_THREADS) Lc[e / k][e % k] = Lcg[e];
   __syncthreads();
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     int64_t a, b;
@@ -62,6 +161,43 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
     } else {
       a = i * P;
       b = a + P;
+    }
+    if (fast) {
+      // a curve observed at every node uses the shared factor: only
+      // Phi^T (Y_i - mu) is formed (strided per thread, then the waves in order)
+      bool missing = false;
+      for (int64_t p = tid; p < P; p += PACE_THREADS) missing |= !isfinite(double(y[a + p]));
+      if (!__syncthreads_or(missing)) {
+        double part[PACE_KMAX];
+#pragma unroll
+        for (int l = 0; l < PACE_KMAX; ++l) part[l] = 0.0;
+        for (int64_t p = tid; p < P; p += PACE_THREADS) {
+          const double ycv = double(y[a + p]) - double(mu[p]);
+#pragma unroll
+          for (int l = 0; l < PACE_KMAX; ++l)
+            if (l < k) part[l] += double(efuns[int64_t(l) * P + p]) * ycv;
+        }
+#pragma unroll
+        for (int l = 0; l < PACE_KMAX; ++l) {
+          if (l >= k) break;
+          double v = part[l];
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if ((tid & 63) == 0) red[tid >> 6][l] = v;
+        }
+        __syncthreads();
+        if (tid < k) {
+          double v = 0.0;
+          for (int w = 0; w < PACE_THREADS / 64; ++w) v += red[w][tid];
+          rhs[tid] = dg.v[tid] >= 0.0 ? v : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          chol_solve(Lc, rhs, k);
+          for (int l = 0; l < k; ++l) scores[i * k + l] = T(rhs[l]);
+        }
+        __syncthreads();  // rhs and red are reused by the next curve
+        continue;
+      }
     }
     double acc[PACE_ACC];
 #pragma unroll
@@ -136,34 +272,8 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
     }
     __syncthreads();
     if (tid == 0) {
-      bool good = true;
-      for (int c = 0; c < k && good; ++c) {  // A = L L^T in place (lower triangle)
-        double d = A[c][c];
-        for (int p = 0; p < c; ++p) d -= A[c][p] * A[c][p];
-        if (!(d > 0.0)) {
-          good = false;
-          break;
-        }
-        const double lc = sqrt(d);
-        A[c][c] = lc;
-        for (int r = c + 1; r < k; ++r) {
-          double s = A[r][c];
-          for (int p = 0; p < c; ++p) s -= A[r][p] * A[c][p];
-          A[r][c] = s / lc;
-        }
-      }
-      if (good) {
-        for (int r = 0; r < k; ++r) {  // L z = rhs
-          double s = rhs[r];
-          for (int p = 0; p < r; ++p) s -= A[r][p] * rhs[p];
-          rhs[r] = s / A[r][r];
-        }
-        for (int r = k - 1; r >= 0; --r) {  // L^T xi = z
-          double s = rhs[r];
-          for (int p = r + 1; p < k; ++p) s -= A[p][r] * rhs[p];
-          rhs[r] = s / A[r][r];
-        }
-      }
+      const bool good = chol_inplace(A, k);
+      if (good) chol_solve(A, rhs, k);
       for (int l = 0; l < k; ++l) scores[i * k + l] = T(good ? rhs[l] : __builtin_nan(""));
     }
   }
@@ -174,9 +284,21 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
               const T *y, const T *mu, const T *efuns, int k, const PaceDiag &dg, T *scores) {
   if (n == 0) return FPCA_OK;
   const GridDims g = make_dims(grid);
+  const double *Lcg = nullptr;
+  const int *cg_ok = nullptr;
+  if (design == FPCA_COMMON_GRID) {
+    if (int rc = ws_reserve(ctx, carve_bytes(PACE_KMAX * PACE_KMAX, 8) + 256)) return rc;
+    Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
+    double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
+    int *okf = cv.take<int>(1);
+    hipLaunchKernelGGL(k_pace_cg_prep<T>, dim3(1), dim3(PACE_THREADS), 0, ctx->stream, g.P, efuns, k, dg, L, okf);
+    FPCA_LAUNCH_CHECK("pace_cg_prep");
+    Lcg = L;
+    cg_ok = okf;
+  }
   const unsigned blocks = unsigned(n < 65536 ? n : 65536);
   hipLaunchKernelGGL(k_pace<T>, dim3(blocks), dim3(PACE_THREADS), 0, ctx->stream, g, n, design, offsets, t, y, mu,
-                     efuns, k, dg, scores);
+                     efuns, k, dg, Lcg, cg_ok, scores);
   FPCA_LAUNCH_CHECK("pace");
   return FPCA_OK;
 }

@@ -89,20 +89,31 @@ def test_pace_irregular(torch, F, h, dt, M, k):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_pace_common_grid(torch, F, h, dt):
-    _say(f"pace common grid {dt}")
-    rng = np.random.default_rng(77)
+@pytest.mark.parametrize("mixed", [False, True])
+def test_pace_common_grid(torch, F, h, dt, mixed):
+    """mixed = False: every curve has missing values (per-curve systems);
+    mixed = True: most curves are complete and take the shared factor, a few
+    have missing values, one component has a negative Ritz value."""
+    _say(f"pace common grid {dt} mixed={mixed}")
+    rng = np.random.default_rng(77 + mixed)
     M = (8, 9)
     P = 72
     n, k = 30, 12
     Y = rng.standard_normal((n, P))
-    Y[rng.random((n, P)) < 0.25] = np.nan
+    if mixed:
+        Y[[2, 11, 19], [5, 40, 71]] = np.nan
+    else:
+        Y[rng.random((n, P)) < 0.25] = np.nan
     Y[7] = np.nan
     mu = rng.standard_normal(P)
     efuns = rng.standard_normal((P, k)) / np.sqrt(P)
     lam = np.linspace(2.0, 0.05, k)
+    if mixed:
+        lam[4] = -0.1
     got, ref = _run(torch, F, h, M, F.FPCA_COMMON_GRID, None, None, Y, mu, efuns, lam, 0.2, dt)
     assert np.all(got[7] == 0)
+    if mixed:
+        assert np.all(got[:, 4] == 0)
     tol = 1e-10 if dt == "f64" else 1e-5
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
@@ -198,3 +209,27 @@ def test_scores_and_reconstruction_end_to_end_c1(torch, F, h):
     fit = (wt * got_xh[curve[:, None], node]).sum(1)
     base = (wt * rmu[node]).sum(1)
     assert np.mean((ds.y - fit) ** 2) < 0.5 * np.mean((ds.y - base) ** 2)
+
+
+def test_pace_common_grid_full_size(torch, F, h):
+    """The benchmark's shape: 5000 complete curves on 64 x 64 nodes, k = 20,
+    FP32 storage; 12 sampled curves against the oracle's N_i x N_i solve
+    (4096 x 4096 per curve)."""
+    _say("pace common grid 64x64 n=5000 k=20")
+    rng = np.random.default_rng(5)
+    M = (64, 64)
+    P = 4096
+    n, k = 5000, 20
+    Y = rng.standard_normal((n, P)).astype(np.float32)
+    mu = (0.1 * rng.standard_normal(P)).astype(np.float32)
+    efuns = (rng.standard_normal((P, k)) / np.sqrt(P)).astype(np.float32)
+    lam = np.geomspace(1.0, 0.01, k)
+    out = torch.empty(n * k, dtype=torch.float32, device="cuda:0")
+    F.fpca_pace_scores(h, F.Grid(M), F.FPCA_COMMON_GRID, F.FPCA_F32, n, None, None, dev(torch, Y), dev(torch, mu),
+                       dev(torch, np.ascontiguousarray(efuns.T)), k, lam, 0.05, out)
+    h.sync()
+    got = out.cpu().numpy().reshape(n, k).astype(np.float64)
+    rows = rng.choice(n, 12, replace=False)
+    ref = oracle.pace_scores(M, None, None, Y[rows].astype(np.float64), mu.astype(np.float64),
+                             efuns.astype(np.float64), lam, 0.05)
+    assert np.abs(got[rows] - ref).max() <= 1e-5 * np.abs(ref).max()
