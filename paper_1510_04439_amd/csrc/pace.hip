@@ -177,12 +177,12 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
           for (int l = 0; l < PACE_KMAX; ++l)
             if (l < k) part[l] += double(efuns[int64_t(l) * P + p]) * ycv;
         }
+        // constant indices throughout, so part[] stays in registers
 #pragma unroll
         for (int l = 0; l < PACE_KMAX; ++l) {
-          if (l >= k) break;
           double v = part[l];
           for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          if ((tid & 63) == 0) red[tid >> 6][l] = v;
+          if ((tid & 63) == 0 && l < k) red[tid >> 6][l] = v;
         }
         __syncthreads();
         if (tid < k) {
@@ -217,7 +217,9 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
           ok = locate(t + j * g.d, g, kk, rho);
           if (ok) {
             nc = 1 << g.d;
-            for (int cc = 0; cc < nc; ++cc) corner(g, kk, rho, cc, &node[cc], &W[cc]);
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+              if (cc < nc) corner(g, kk, rho, cc, &node[cc], &W[cc]);
           }
         } else {
           nc = 1;
@@ -227,13 +229,19 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
         const double yv = double(y[j]);
         ok = ok && isfinite(yv);
         double mv = 0.0;
-        if (ok)
-          for (int cc = 0; cc < nc; ++cc) mv += W[cc] * double(mu[node[cc]]);
+        if (ok) {
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc)
+            if (cc < nc) mv += W[cc] * double(mu[node[cc]]);
+        }
         yc[tid] = ok ? yv - mv : 0.0;
         for (int l = 0; l < k; ++l) {
           double v = 0.0;
-          if (ok)
-            for (int cc = 0; cc < nc; ++cc) v += W[cc] * double(efuns[int64_t(l) * P + node[cc]]);
+          if (ok) {
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+              if (cc < nc) v += W[cc] * double(efuns[int64_t(l) * P + node[cc]]);
+          }
           ph[tid][l] = v;
         }
       }
