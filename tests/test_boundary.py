@@ -58,3 +58,31 @@ def test_create_without_device_fails_cleanly():
     with pytest.raises(F.FpcaError) as e:
         F.Handle(0)
     assert e.value.code in (F.FPCA_ERR_DEVICE, F.FPCA_ERR_INVALID_ARG)
+
+
+def test_noise_pace_reconstruct_reject_null_handle():
+    import paper_1510_04439_amd as F
+    from paper_1510_04439_amd._binding import _GridC
+    lib = F.load_library()
+    g = _GridC()
+    g.d = 1
+    g.M[0], g.M[1], g.M[2] = 9, 1, 1
+    s2 = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    assert lib.fpca_noise_variance(None, ctypes.byref(g), 1, None, None, None, None, ctypes.byref(s2),
+                                   ctypes.byref(cnt)) == F.FPCA_ERR_INVALID_ARG
+    ev = (ctypes.c_double * 2)(1.0, 0.5)
+    assert lib.fpca_pace_scores(None, ctypes.byref(g), 1, 1, 2, None, None, None, None, None, 2, ev, 0.1,
+                                None) == F.FPCA_ERR_INVALID_ARG
+    assert lib.fpca_reconstruct(None, 1, 9, 2, 2, None, None, None, None) == F.FPCA_ERR_INVALID_ARG
+    assert b"handle" in lib.fpca_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
