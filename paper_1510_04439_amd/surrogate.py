@@ -201,11 +201,27 @@ def label_many(h: B.Handle, split: str, count: int, n_scale: float, start: int =
     return (np.array(feats), np.array(labels), np.array(scores), np.array(qtot), np.array(meta))
 
 
-def evaluate(h: B.Handle, model: Surrogate, split: str, count: int, n_scale: float, start: int = 0):
+def hdep_loss(score, s_min, q):
+    """Loss of a selected bandwidth on the h-dependent part of the CV score:
+    (CV(h) - min_grid CV) / |min_grid CV - q|, with q the h-independent sum of
+    the held-out squared products (0 at the grid optimum, > 0 when worse)."""
+    return (score - s_min) / abs(s_min - q)
+
+
+def best_constant_h(scores: np.ndarray, qtot: np.ndarray) -> float:
+    """The bandwidth of H_GRID with the smallest mean h-dependent loss over
+    labelled (training) datasets: the best selector that ignores the data."""
+    smin = scores.min(axis=1)
+    loss = (scores - smin[:, None]) / np.abs(smin - qtot)[:, None]
+    return float(H_GRID[int(np.argmin(loss.mean(axis=0)))])
+
+
+def evaluate(h: B.Handle, model: Surrogate, split: str, count: int, n_scale: float, start: int = 0,
+             h_const: Optional[float] = None):
     """Held-out comparison of surrogate selection against batched CV: CV-score
-    ratio CV(h_sur)/min_grid CV, the same ratio on the h-dependent part (the
-    score minus the h-independent sum of Q), |log h_sur - log h_CV| and the
-    times of both selectors (after the shared binning)."""
+    ratio CV(h_sur)/min_grid CV, the loss on the h-dependent part (hdep_loss)
+    for the surrogate and for a constant bandwidth, |log h_sur - log h_CV| and
+    the times of both selectors (after the shared binning)."""
     import torch
     from fpca_synth import make_surrogate_dataset
     rows = []
@@ -224,9 +240,13 @@ def evaluate(h: B.Handle, model: Surrogate, split: str, count: int, n_scale: flo
         s_sur = float(cv_scores(h, bd, [hs])[0])
         s_min = float(sc.min())
         q = float(bd.Q[1:].sum(dtype=torch.float64).item())
-        rows.append(dict(n=ds.n, h_sur=hs, h_cv=h_cv, fallback=fb, ratio=s_sur / s_min,
-                         excess_ratio=(s_sur - q) / (s_min - q), dlogh=abs(math.log(hs) - math.log(h_cv)),
-                         t_sur=t_sur, t_cv=t_cv))
+        row = dict(n=ds.n, h_sur=hs, h_cv=h_cv, fallback=fb, ratio=s_sur / s_min,
+                   loss=hdep_loss(s_sur, s_min, q), dlogh=abs(math.log(hs) - math.log(h_cv)),
+                   t_sur=t_sur, t_cv=t_cv)
+        if h_const is not None:
+            s_c = float(sc[int(np.argmin(np.abs(H_GRID - h_const)))])
+            row.update(const_ratio=s_c / s_min, const_loss=hdep_loss(s_c, s_min, q))
+        rows.append(row)
         if (i - start + 1) % 50 == 0:
             log(f"evaluated {i - start + 1}/{count}")
     return rows
@@ -234,15 +254,23 @@ def evaluate(h: B.Handle, model: Surrogate, split: str, count: int, n_scale: flo
 
 def summarize(rows):
     r = np.array([x["ratio"] for x in rows])
-    e = np.array([x["excess_ratio"] for x in rows])
+    e = np.array([x["loss"] for x in rows])
     d = np.array([x["dlogh"] for x in rows])
     ts = np.array([x["t_sur"] for x in rows])
     tc = np.array([x["t_cv"] for x in rows])
-    return dict(count=len(rows), ratio_mean=float(r.mean()), ratio_p95=float(np.percentile(r, 95)),
-                excess_ratio_mean=float(e.mean()), excess_ratio_p95=float(np.percentile(e, 95)),
-                dlogh_mean=float(d.mean()), fallback_rate=float(np.mean([x["fallback"] for x in rows])),
-                t_sur_ms_median=float(np.median(ts) * 1e3), t_cv_ms_median=float(np.median(tc) * 1e3),
-                speedup_median=float(np.median(tc / ts)))
+    out = dict(count=len(rows), ratio_mean=float(r.mean()), ratio_p95=float(np.percentile(r, 95)),
+               ratio_max=float(r.max()),
+               hdep_loss_mean=float(e.mean()), hdep_loss_p95=float(np.percentile(e, 95)),
+               hdep_loss_max=float(e.max()),
+               dlogh_mean=float(d.mean()), fallback_rate=float(np.mean([x["fallback"] for x in rows])),
+               t_sur_ms_median=float(np.median(ts) * 1e3), t_cv_ms_median=float(np.median(tc) * 1e3),
+               speedup_median=float(np.median(tc / ts)))
+    if rows and "const_loss" in rows[0]:
+        c = np.array([x["const_loss"] for x in rows])
+        cr = np.array([x["const_ratio"] for x in rows])
+        out.update(const_hdep_loss_mean=float(c.mean()), const_hdep_loss_p95=float(np.percentile(c, 95)),
+                   const_hdep_loss_max=float(c.max()), const_ratio_max=float(cr.max()))
+    return out
 
 
 def main(argv=None):
@@ -255,12 +283,29 @@ def main(argv=None):
     ap.add_argument("--labels-out", default=None, help="save the training labels (npz) and stop")
     ap.add_argument("--labels-in", default=None,
                     help="comma-separated label files from --labels-out to train on (no labelling)")
+    ap.add_argument("--model-in", default=None, help="evaluate this trained model (no labelling or training)")
+    ap.add_argument("--n-const", type=int, default=500,
+                    help="training datasets labelled to choose the constant-bandwidth baseline")
     ap.add_argument("--out", default="gpurun_out/bw_surrogate.npz")
     ap.add_argument("--report", default="gpurun_out/bw_surrogate.json")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available()
     h = B.Handle(0)
+    if args.model_in:
+        model = Surrogate.load(args.model_in)
+        _, _, sc_c, q_c, _ = label_many(h, "train", args.n_const, args.n_scale, start=0)
+        h_const = best_constant_h(sc_c, q_c)
+        log(f"constant-bandwidth baseline from {args.n_const} training datasets: h = {h_const:.4f}")
+        rows = evaluate(h, model, "test", args.n_test, args.n_scale, h_const=h_const)
+        summ = summarize(rows)
+        summ.update(model=os.path.basename(args.model_in), h_grid=H_GRID.tolist(), h_const=h_const,
+                    n_const=args.n_const)
+        with open(args.report, "w") as fh:
+            json.dump(dict(summary=summ, rows=rows), fh)
+        log(json.dumps(summ))
+        h.close()
+        return
     if args.labels_in:
         parts = [np.load(f) for f in args.labels_in.split(",")]
         ftr = np.concatenate([z["feats"] for z in parts])

@@ -59,6 +59,25 @@ def test_end_to_end_d2_irregular(torch, F, h):
     ev, phi, fve = oracle.eig_randomized(np.nan_to_num(gam), om, ds.k, ds.oversample, ds.power_iters,
                                          ds.rp_seed)
     assert np.abs(bufs.evals[:6] - ev[:6]).max() <= 1e-4 * ev[0]
+    # eigenfunctions of the whole chain, with a tolerance that grows as the
+    # neighbouring eigenvalues close in (a perturbation of the surface by e
+    # turns an eigenvector by about e / gap)
+    phi_gpu = bufs.efuns.cpu().numpy()
+    for j in range(6):
+        gap = min(abs(ev[j] - ev[j - 1]) if j else np.inf, abs(ev[j] - ev[j + 1]))
+        scale = max(1.0, 0.1 * ev[0] / gap)
+        err = min(np.abs(phi_gpu[j] - phi[:, j]).max(), np.abs(phi_gpu[j] + phi[:, j]).max())
+        assert err <= 1e-2 * scale * np.abs(phi[:, j]).max(), (j, err, scale)
+    # the eigendecomposition alone: the oracle's randomized eig of the GPU's own surface
+    gam_gpu = bufs.gamma.cpu().numpy().astype(np.float64)
+    ev2, phi2, fve2 = oracle.eig_randomized(np.nan_to_num(gam_gpu), om, ds.k, ds.oversample, ds.power_iters,
+                                            ds.rp_seed)
+    assert np.abs(bufs.evals - ev2).max() <= 1e-5 * ev2[0]
+    for j in range(ds.k):
+        gap = min(abs(ev2[j] - ev2[j - 1]) if j else np.inf, abs(ev2[j] - ev2[j + 1]) if j + 1 < ds.k else np.inf)
+        scale = max(1.0, 0.1 * ev2[0] / gap)
+        err = min(np.abs(phi_gpu[j] - phi2[:, j]).max(), np.abs(phi_gpu[j] + phi2[:, j]).max())
+        assert err <= 1e-3 * scale * np.abs(phi2[:, j]).max(), (j, err, scale)
 
 
 def test_d3_masked_mean(torch, F, h):

@@ -97,17 +97,26 @@ def test_mlp_forward_backward_adam(torch, F, h):
 
 
 def test_trained_surrogate_gain(torch, F, h):
-    """The committed model against the method without it (batched CV over 16
-    bandwidths x 5 folds, the grid argmin) on held-out datasets outside its
-    evaluation set: the CV score at the surrogate's h stays within 2% of the
-    grid minimum, and the selection (features + MLP) is at least 5x faster
-    than batched CV after the shared binning (about 200x measured)."""
+    """The committed model against the method without it, on held-out datasets
+    outside its evaluation set. Loss is measured on the h-dependent part of the
+    CV score, (CV(h) - min_grid CV) / |min_grid CV - q| with q the h-independent
+    sum of the held-out squared products (the total score is dominated by q, so
+    a data-blind bandwidth passes a ratio test on it). The surrogate must beat
+    the best constant bandwidth (chosen on training datasets and stored with the
+    evaluation) on mean loss, keep the total CV score within 2% of the grid
+    minimum, and select at least 20x faster than batched CV after the shared
+    binning."""
+    import json
+    import os
     import time
     from paper_1510_04439_amd import surrogate as S
     from fpca_synth import make_surrogate_dataset
+    with open(os.path.join(os.path.dirname(S.MODEL_PATH), "bw_surrogate_eval.json")) as fh:
+        h_const = float(json.load(fh)["h_const"])
+    jc = int(np.argmin(np.abs(S.H_GRID - h_const)))
     model = S.Surrogate.load()
-    t_sur, t_cv = [], []
-    for i in (1000, 1001, 1002):
+    t_sur, t_cv, l_sur, l_const = [], [], [], []
+    for i in range(1000, 1008):
         print(f"surrogate gain dataset test-{i}", flush=True)
         bd = S.bin_dataset(h, make_surrogate_dataset(i, "test"))
         S.cv_scores(h, bd, S.H_GRID[:1])
@@ -121,6 +130,13 @@ def test_trained_surrogate_gain(torch, F, h):
         sc = S.cv_scores(h, bd, S.H_GRID)
         t_cv.append(time.perf_counter() - t0)
         assert not fb
-        ratio = float(S.cv_scores(h, bd, [hs])[0]) / float(sc.min())
-        assert ratio <= 1.02, (i, hs, ratio)
-    assert np.median(t_cv) / np.median(t_sur) >= 5.0, (t_cv, t_sur)
+        s_sur = float(S.cv_scores(h, bd, [hs])[0])
+        s_min = float(sc.min())
+        q = float(bd.Q[1:].sum(dtype=torch.float64).item())
+        assert s_sur / s_min <= 1.02, (i, hs, s_sur / s_min)
+        l_sur.append(S.hdep_loss(s_sur, s_min, q))
+        l_const.append(S.hdep_loss(float(sc[jc]), s_min, q))
+    print(f"h-dependent loss: surrogate mean {np.mean(l_sur):.4f} max {np.max(l_sur):.4f}; "
+          f"constant h={h_const:.3f} mean {np.mean(l_const):.4f} max {np.max(l_const):.4f}", flush=True)
+    assert np.mean(l_sur) < np.mean(l_const), (l_sur, l_const)
+    assert np.median(t_cv) / np.median(t_sur) >= 20.0, (t_cv, t_sur)

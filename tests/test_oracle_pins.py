@@ -156,7 +156,7 @@ def test_common_grid_closed_form():
 
 # ------------------------------------------------------------------ P4 linear reproduction
 @pytest.mark.parametrize("dims,h", [((23,), 0.13), ((9, 11), 0.3), ((5, 6, 7), 0.45),
-                                    ((7, 6, 7, 6), 0.4)])
+                                    ((7, 6, 7, 6), 0.4), ((5, 4, 5, 4, 5), 0.5), ((4, 5, 4, 4, 5, 4), 0.6)])
 def test_local_linear_reproduces_linear_functions(dims, h):
     """If g_p = c_p (a + b^T x_p) then b0(x) = a + b^T x at every node with an OK
     status -- boundaries included (Fan & Gijbels' reproduction property)."""
@@ -457,6 +457,40 @@ def test_features_lag_structure_and_counts():
     np.testing.assert_allclose(f[12:12 + 5], rho ** np.arange(1, 6), rtol=1e-12)
     np.testing.assert_allclose(f[20:20 + 4], rho ** np.arange(1, 5), rtol=1e-12)
     assert abs(f[9] - np.log(2.0)) < 1e-12 and abs(f[10] - (3.0 - 2.0) / 3.0) < 1e-12
+    # curvature of the variogram at lag 0: (2 rho^2 - 4 rho + 2) / 2 = (1 - rho)^2 along both coordinates
+    assert abs(f[28] - (1 - rho) ** 2) < 1e-12 and abs(f[29] - (1 - rho) ** 2) < 1e-12
+    # pair-weight level: sum C = P^2 + 0.1 P (sum of first coordinates + sum of second coordinates)
+    #                          = 900 + 3 (5 * 15 + 6 * 10) = 1305
+    assert abs(f[30] - np.log(1305.0 / 900.0)) < 1e-12
+    assert abs(f[31] - np.log(1.0 / 5.0)) < 1e-15 and abs(f[4] - np.log(30.0)) < 1e-15
+
+
+def test_features_occupancy_moments_and_spread():
+    """Hand-built arrays with known values of the curve-size spread, occupancy,
+    pair density, response moments and the raw-product variance."""
+    from oracle import mlp
+    M = (6, 5)
+    P = 30
+    off = np.array([0, 3, 7, 12], np.int64)           # N_i = 3, 4, 5
+    c = np.zeros(P)
+    c[:12] = 2.0                                       # 12 of 30 nodes occupied, equal weights
+    s = 0.5 * c                                        # E Y = 0.5
+    s2 = 3.0 * c                                       # E Y^2 = 3
+    C = np.ones((P, P))
+    C[:5, :] = 0.0                                     # 150 of 900 pair cells empty
+    a, tau = 0.8, 0.09
+    G = a * C                                          # raw products a on every pair
+    Q = (a * a + tau) * C                              # squared products: variance tau about a
+    f = mlp.features(M, off, c, s, s2, C, G, Q)
+    assert abs(f[1] - np.log(4.0)) < 1e-15
+    assert abs(f[3] - np.sqrt(2.0 / 3.0) / 4.0) < 1e-15   # E N^2 = 50/3, (E N)^2 = 16
+    assert abs(f[5] - 12.0 / 30.0) < 1e-15
+    assert abs(f[6] - 750.0 / 900.0) < 1e-15
+    assert abs(f[7] - np.log(3.0)) < 1e-15
+    assert abs(f[8] - 0.25 / 3.0) < 1e-15
+    assert abs(f[11] - np.log(tau)) < 1e-12
+    # without Q the raw-product variance feature is left at 0
+    assert mlp.features(M, off, c, s, s2, C, G)[11] == 0.0
 
 
 # ------------------------------------------------------------------ noise variance (eq. 2.6)
