@@ -260,6 +260,22 @@ int fpca_pace_scores(fpca_handle handle, const fpca_grid *grid, int design, int 
                      int k, const double *evals, double sigma2, void *scores);
 
 /*
+ * fpca_pace_scores_noalloc -- fpca_pace_scores for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, same kernels and the same
+ * results, but no allocation of any kind. The common-grid design's shared
+ * k x k factor lives in a fixed per-GPU array of 8,448 bytes (k <= 32, the
+ * limit of fpca_pace_scores, so every valid call fits), set up by
+ * fpca_create and held until the process ends; the irregular design needs
+ * none. Every call on one GPU uses that GPU's array: calls that overlap in
+ * time on one GPU (several streams or handles) race and must be serialized
+ * by the caller. Errors as for fpca_pace_scores.
+ */
+int fpca_pace_scores_noalloc(fpca_handle handle, const fpca_grid *grid, int design, int dtype, int64_t n,
+                             const int64_t *offsets, const void *t, const void *y, const void *mu,
+                             const void *efuns, int k, const double *evals, double sigma2, void *scores);
+
+/*
  * fpca_reconstruct -- curves on the grid from their scores (the display after
  * eq. 2.7): xhat[i][p] = mu[p] + sum_{l < k} scores[i][l] efuns_l[p].
  *   mu: device, P; efuns: device, P x k column-major; scores: device, n x k

@@ -15,5 +15,5 @@ from ._binding import (  # noqa: F401
     EXPORTED_SYMBOLS, fpca_bin, fpca_cv_batched, fpca_eig_randomized, fpca_rng_normal, fpca_smooth_cov,
     fpca_smooth_mean, load_library, fpca_bw_features, fpca_bw_num_params, fpca_bw_mlp_forward,
     fpca_bw_mlp_backward, fpca_bw_adam_step, fpca_noise_variance,
-    fpca_pace_scores, fpca_reconstruct,
+    fpca_pace_scores, fpca_pace_scores_noalloc, fpca_reconstruct,
 )

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
-    "fpca_reconstruct",
+    "fpca_reconstruct", "fpca_pace_scores_noalloc",
 ]
 
 
@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH):
     L.fpca_reconstruct.argtypes = [vp, i32, i64, i64, i32, vp, vp, vp, vp]
     L.fpca_pace_scores.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
+    L.fpca_pace_scores_noalloc.argtypes = L.fpca_pace_scores.argtypes
     L.fpca_noise_variance.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, vp,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.fpca_last_error.restype = ctypes.c_char_p
@@ -218,6 +219,15 @@ def fpca_pace_scores(h: Handle, grid: Grid, design: int, dtype: int, n: int, off
     _check(load_library().fpca_pace_scores(h.ptr, ctypes.byref(g), int(design), int(dtype), int(n), _ptr(offsets),
                                            _ptr(t), _ptr(y), _ptr(mu), _ptr(efuns), int(k), ev, float(sigma2),
                                            _ptr(scores)))
+
+
+def fpca_pace_scores_noalloc(h: Handle, grid: Grid, design: int, dtype: int, n: int, offsets, t, y, mu, efuns,
+                             k: int, evals, sigma2: float, scores):
+    g = grid.c()
+    ev = (ctypes.c_double * k)(*[float(v) for v in np.asarray(evals, np.float64)[:k]])
+    _check(load_library().fpca_pace_scores_noalloc(h.ptr, ctypes.byref(g), int(design), int(dtype), int(n),
+                                                   _ptr(offsets), _ptr(t), _ptr(y), _ptr(mu), _ptr(efuns), int(k),
+                                                   ev, float(sigma2), _ptr(scores)))
 
 
 def fpca_reconstruct(h: Handle, dtype: int, P: int, n: int, k: int, mu, efuns, scores, xhat):

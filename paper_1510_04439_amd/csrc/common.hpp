@@ -83,6 +83,8 @@ struct Carver {
 inline size_t carve_bytes(size_t count, size_t elem) { return (count * elem + 255) & ~size_t(255); }
 
 int check_handle(fpca_context *ctx);
+// Device address of the allocation-free PACE scratch (pace.hip), per device.
+int pace_scratch_init(int device);
 int check_grid(const fpca_grid *g, int64_t *P);
 int set_device(fpca_context *ctx);
 

@@ -156,6 +156,7 @@ int fpca_create(fpca_handle *handle, int device) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return set_error(FPCA_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
                      prop.gcnArchName);
+  if (int rc = pace_scratch_init(device)) return rc;
   auto *ctx = new fpca_context();
   ctx->device = device;
   ctx->num_cus = prop.multiProcessorCount;

@@ -9,6 +9,8 @@
 // turns the N_i x N_i system into a k x k one:
 //   (Phi_i^T Phi_i + sigma^2 Lambda^{-1}) xi_i = Phi_i^T (Y_i - mu_i).
 // Components with lambda_l <= 0 are left out of Sigma_i and score 0.
+#include <mutex>
+
 #include "binrule.hpp"
 #include "common.hpp"
 
@@ -287,16 +289,22 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
   }
 }
 
+// Scratch of the common-grid design: the shared k x k factor and its flag.
+constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256;
+
+// `fixed`: caller-provided scratch of PACE_SCRATCH_BYTES (the allocation-free
+// entry point), or NULL to carve it from the handle's arena.
 template <typename T>
 int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, const int64_t *offsets, const T *t,
-              const T *y, const T *mu, const T *efuns, int k, const PaceDiag &dg, T *scores) {
+              const T *y, const T *mu, const T *efuns, int k, const PaceDiag &dg, T *scores, void *fixed) {
   if (n == 0) return FPCA_OK;
   const GridDims g = make_dims(grid);
   const double *Lcg = nullptr;
   const int *cg_ok = nullptr;
   if (design == FPCA_COMMON_GRID) {
-    if (int rc = ws_reserve(ctx, carve_bytes(PACE_KMAX * PACE_KMAX, 8) + 256)) return rc;
-    Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
+    if (!fixed)
+      if (int rc = ws_reserve(ctx, PACE_SCRATCH_BYTES)) return rc;
+    Carver cv{static_cast<char *>(fixed ? fixed : ctx->ws), 0, fixed ? PACE_SCRATCH_BYTES : ctx->ws_size};
     double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
     int *okf = cv.take<int>(1);
     hipLaunchKernelGGL(k_pace_cg_prep<T>, dim3(1), dim3(PACE_THREADS), 0, ctx->stream, g.P, efuns, k, dg, L, okf);
@@ -353,15 +361,40 @@ int reconstruct_impl(fpca_context *ctx, int64_t P, int64_t n, int k, const T *mu
   return FPCA_OK;
 }
 
+// One copy per GPU of the scratch used by fpca_pace_scores_noalloc. In host
+// code `scratch` names a host-side stand-in: kernels get the device address
+// looked up for each device by pace_scratch_init.
+constexpr int PACE_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[PACE_MAX_DEVICES] = {};
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[PACE_SCRATCH_BYTES];
+
+// Looks up this device's address of `scratch` (the device must be current).
+// Called by fpca_create, once per device.
+int pace_scratch_init(int device) {
+  if (device < 0 || device >= PACE_MAX_DEVICES)
+    return set_error(FPCA_ERR_UNSUPPORTED, "device %d beyond the %d supported", device, PACE_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return FPCA_OK;
+  void *ptr = nullptr;
+  FPCA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return set_error(FPCA_ERR_DEVICE, "no device address for the PACE scratch");
+  g_scratch_ptr[device] = ptr;
+  return FPCA_OK;
+}
 
 }  // namespace fpca
 
 using namespace fpca;
 
-extern "C" int fpca_pace_scores(fpca_handle ctx, const fpca_grid *grid, int design, int dtype, int64_t n,
-                                const int64_t *offsets, const void *t, const void *y, const void *mu,
-                                const void *efuns, int k, const double *evals, double sigma2, void *scores) {
+namespace {
+
+int pace_entry(fpca_handle ctx, const fpca_grid *grid, int design, int dtype, int64_t n, const int64_t *offsets,
+               const void *t, const void *y, const void *mu, const void *efuns, int k, const double *evals,
+               double sigma2, void *scores, bool no_alloc) {
   if (int rc = check_handle(ctx)) return rc;
   int64_t P;
   if (int rc = check_grid(grid, &P)) return rc;
@@ -383,13 +416,34 @@ extern "C" int fpca_pace_scores(fpca_handle ctx, const fpca_grid *grid, int desi
   for (int l = 0; l < k; ++l)
     if (evals[l] > 0.0 && std::isfinite(evals[l])) dg.v[l] = sigma2 / evals[l];
   if (int rc = set_device(ctx)) return rc;
+  void *fixed = nullptr;
+  if (no_alloc) {
+    // k <= PACE_KMAX was checked above, so the fixed scratch always suffices
+    fixed = (ctx->device >= 0 && ctx->device < PACE_MAX_DEVICES) ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!fixed) return set_error(FPCA_ERR_DEVICE, "PACE scratch not set up on device %d", ctx->device);
+  }
   if (dtype == FPCA_F64)
     return pace_impl<double>(ctx, grid, design, n, offsets, static_cast<const double *>(t),
                              static_cast<const double *>(y), static_cast<const double *>(mu),
-                             static_cast<const double *>(efuns), k, dg, static_cast<double *>(scores));
+                             static_cast<const double *>(efuns), k, dg, static_cast<double *>(scores), fixed);
   return pace_impl<float>(ctx, grid, design, n, offsets, static_cast<const float *>(t), static_cast<const float *>(y),
                           static_cast<const float *>(mu), static_cast<const float *>(efuns), k, dg,
-                          static_cast<float *>(scores));
+                          static_cast<float *>(scores), fixed);
+}
+
+}  // namespace
+
+extern "C" int fpca_pace_scores(fpca_handle ctx, const fpca_grid *grid, int design, int dtype, int64_t n,
+                                const int64_t *offsets, const void *t, const void *y, const void *mu,
+                                const void *efuns, int k, const double *evals, double sigma2, void *scores) {
+  return pace_entry(ctx, grid, design, dtype, n, offsets, t, y, mu, efuns, k, evals, sigma2, scores, false);
+}
+
+extern "C" int fpca_pace_scores_noalloc(fpca_handle ctx, const fpca_grid *grid, int design, int dtype, int64_t n,
+                                        const int64_t *offsets, const void *t, const void *y, const void *mu,
+                                        const void *efuns, int k, const double *evals, double sigma2,
+                                        void *scores) {
+  return pace_entry(ctx, grid, design, dtype, n, offsets, t, y, mu, efuns, k, evals, sigma2, scores, true);
 }
 
 extern "C" int fpca_reconstruct(fpca_handle ctx, int dtype, int64_t P, int64_t n, int k, const void *mu,
