@@ -288,19 +288,45 @@ int fpca_reconstruct(fpca_handle handle, int dtype, int64_t P, int64_t n, int k,
 /*
  * fpca_cv_batched -- bandwidth selection for the covariance smoother by
  * leave-curves-out cross-validation (the CV idea of Section 3.3, on folds of
- * curves and binned data). For every bandwidth h (row of `bandwidths`) and
- * fold f, the smoother of eq. 2.4 is fitted to the pairs of the curves outside
- * fold f, C - C_f and G - G_f, giving Ghat; the held-out pairs are scored
- * through their bins:
- *   scores[h * n_folds + f] = sum_{p,q} Q_f - 2 G_f Ghat + C_f Ghat^2
+ * curves and binned data), over several datasets at once. For every dataset
+ * a, bandwidth h (row of `bandwidths`) and fold f, the smoother of eq. 2.4 is
+ * fitted to the pairs of the curves outside fold f, C - C_f and G - G_f,
+ * giving Ghat (symmetrized, 0 outside the dataset's mask); the held-out pairs
+ * are scored through their bins:
+ *   scores[(a * n_h + h) * n_folds + f] = sum_{p,q} Q_f - 2 G_f Ghat + C_f Ghat^2
  * (= sum over held-out pairs of w (Y_ij Y_il - Ghat)^2 spread over the pair's
  * bins; Ghat is taken as 0 where the window is empty), accumulated in FP64.
- *   C, G, Q: (n_folds+1) x P x P device arrays from fpca_bin(kind = COV) with
- *     folds and sq_sums (slab 0 all curves, slab f+1 fold f).
- *   bandwidths: host, n_h x d. scores: host, n_h x n_folds. Synchronizes.
+ *   data: host array of n_data datasets. Each has its own grid (and mask;
+ *     every dataset has the same d, grid sizes may differ) and its C, G, Q:
+ *     (n_folds+1) x P x P device arrays of `dtype` from fpca_bin(kind = COV)
+ *     with folds and sq_sums (slab 0 all curves, slab f+1 fold f).
+ *   bandwidths: host, n_h x d, shared by the datasets. scores: host,
+ *     n_data x n_h x n_folds.
+ * All jobs run in one persistent launch on the handle's stream (moments and
+ * solves in FP64); the tile shape is chosen by timing on the first call with a
+ * shape, the second call captures the launch into a HIP graph and later calls
+ * replay it. Grids with more than 4096 nodes, or a first coordinate longer
+ * than the launch's LDS allows (d = 1: 64, d = 2: 32, d = 3: 16), run job by
+ * job instead. Synchronizes; FPCA_ERR_DEVICE if a task of the launch waited
+ * past its spin limit.
  */
-int fpca_cv_batched(fpca_handle handle, const fpca_grid *grid, int dtype, int n_folds, const void *C,
-                    const void *G, const void *Q, int n_h, const double *bandwidths, double *scores);
+typedef struct {
+  fpca_grid grid;
+  const void *C, *G, *Q;
+} fpca_cv_data;
+
+int fpca_cv_batched(fpca_handle handle, int dtype, int n_data, const fpca_cv_data *data, int n_folds, int n_h,
+                    const double *bandwidths, double *scores);
+
+/*
+ * fpca_cv_select -- the selected bandwidth from a CV curve (host only): the
+ * grid minimizer of cv[n_h] (scores summed over folds), refined by the vertex
+ * of the parabola through it and its two neighbours in log h when the minimum
+ * is interior and the parabola opens upward (clamped to the neighbours). The
+ * rows of `bandwidths` (n_h x d) must be positive multiples of one vector,
+ * increasing; the refinement moves along that ray. h_out: d doubles.
+ */
+int fpca_cv_select(int n_h, int d, const double *bandwidths, const double *cv, double *h_out);
 
 /*
  * Bandwidth surrogate (an addition to the paper's method, whose Section 3.3

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
-    "fpca_reconstruct", "fpca_pace_scores_noalloc",
+    "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select",
 ]
 
 
@@ -45,6 +45,10 @@ class FpcaError(RuntimeError):
 
 class _GridC(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("M", ctypes.c_int * 3), ("mask", ctypes.c_void_p)]
+
+
+class _CvDataC(ctypes.Structure):
+    _fields_ = [("grid", _GridC), ("C", ctypes.c_void_p), ("G", ctypes.c_void_p), ("Q", ctypes.c_void_p)]
 
 
 _lib = None
@@ -80,8 +84,10 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_double), vp,
                                       ctypes.POINTER(ctypes.c_double)]
     L.fpca_rng_normal.argtypes = [vp, u64, i64, vp]
-    L.fpca_cv_batched.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, vp, vp, vp, i32,
+    L.fpca_cv_batched.argtypes = [vp, i32, i32, ctypes.POINTER(_CvDataC), i32, i32,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.fpca_cv_select.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
     L.fpca_bw_features.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fpca_bw_num_params.argtypes = []
     L.fpca_bw_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -268,16 +274,37 @@ def fpca_bw_adam_step(h: Handle, step: int, lr: float, beta1: float, beta2: floa
                                             _ptr(grad), _ptr(m), _ptr(v)))
 
 
-def fpca_cv_batched(h: Handle, grid: Grid, dtype: int, n_folds: int, C, G, Q, bandwidths):
-    """bandwidths: n_h x d (or n_h scalars shared by all coordinates). Returns scores (n_h x n_folds)."""
+def _bw_rows(bandwidths, d):
     bw = np.asarray(bandwidths, np.float64)
     if bw.ndim == 1:
-        bw = np.repeat(bw[:, None], grid.d, axis=1)
-    bw = np.ascontiguousarray(bw)
+        bw = np.repeat(bw[:, None], d, axis=1)
+    return np.ascontiguousarray(bw)
+
+
+def fpca_cv_batched(h: Handle, dtype: int, data, n_folds: int, bandwidths):
+    """data: list of (Grid, C, G, Q) per dataset; bandwidths: n_h x d (or n_h
+    scalars shared by all coordinates). Returns scores (n_data x n_h x n_folds)."""
+    data = list(data)
+    d = data[0][0].d
+    bw = _bw_rows(bandwidths, d)
     n_h = bw.shape[0]
-    out = np.zeros(n_h * n_folds)
-    g = grid.c()
-    _check(load_library().fpca_cv_batched(h.ptr, ctypes.byref(g), dtype, int(n_folds), _ptr(C), _ptr(G), _ptr(Q),
-                                          n_h, bw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+    arr = (_CvDataC * len(data))()
+    for i, (grid, C, G, Q) in enumerate(data):
+        arr[i].grid = grid.c()
+        arr[i].C, arr[i].G, arr[i].Q = _ptr(C), _ptr(G), _ptr(Q)
+    out = np.zeros(len(data) * n_h * n_folds)
+    _check(load_library().fpca_cv_batched(h.ptr, int(dtype), len(data), arr, int(n_folds), n_h,
+                                          bw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-    return out.reshape(n_h, n_folds)
+    return out.reshape(len(data), n_h, n_folds)
+
+
+def fpca_cv_select(bandwidths, cv, d: int = 1) -> np.ndarray:
+    """Refined CV bandwidth (n_h rows on a ray, cv summed over folds); returns d values."""
+    bw = _bw_rows(bandwidths, d)
+    cvv = np.ascontiguousarray(np.asarray(cv, np.float64))
+    out = np.zeros(d)
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().fpca_cv_select(bw.shape[0], d, bw.ctypes.data_as(P), cvv.ctypes.data_as(P),
+                                         out.ctypes.data_as(P)))
+    return out

@@ -38,6 +38,13 @@ struct fpca_context {
   static constexpr size_t kStageBytes = 4096;
   double *h_stage = nullptr;
   int num_cus = 256;
+  // Pinned staging of the task-queue tables (grows); ev_tables marks the
+  // last upload from it, so it is not rewritten while a copy is pending.
+  void *h_tables = nullptr;
+  size_t h_tables_size = 0;
+  hipEvent_t ev_tables = nullptr;
+  // Tile shapes chosen by the autotuner, per batched-CV shape key.
+  std::vector<std::pair<std::vector<double>, std::pair<int, int>>> tune_cache;
 };
 
 namespace fpca {
@@ -61,6 +68,9 @@ int hip_fail(hipError_t e, const char *what);
 int ws_reserve(fpca_context *ctx, size_t bytes);
 int ws2_reserve(fpca_context *ctx, size_t bytes);
 int ws3_reserve(fpca_context *ctx, size_t bytes);
+// Pinned host staging of at least `bytes` for table uploads; waits for the
+// previous upload from it first.
+int tables_stage(fpca_context *ctx, size_t bytes, char **out);
 
 // Covariance smoother behind fpca_smooth_cov (arguments already validated).
 int smooth_cov_internal(fpca_context *ctx, const fpca_grid *grid, int dtype, const void *C, double c_uniform,

@@ -1,6 +1,7 @@
 // Handle, error reporting, scratch arena and small fill kernels.
 #include <cstdarg>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 
 #include "common.hpp"
@@ -107,6 +108,26 @@ static int arena_reserve(fpca_context *ctx, void **arena, size_t *size, size_t b
   return FPCA_OK;
 }
 
+int tables_stage(fpca_context *ctx, size_t bytes, char **out) {
+  if (!ctx->ev_tables) FPCA_HIP(hipEventCreateWithFlags(&ctx->ev_tables, hipEventDisableTiming));
+  else FPCA_HIP(hipEventSynchronize(ctx->ev_tables));
+  if (bytes > ctx->h_tables_size) {
+    if (ctx->h_tables) FPCA_HIP(hipHostFree(ctx->h_tables));
+    ctx->h_tables = nullptr;
+    ctx->h_tables_size = 0;
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    hipError_t e = hipHostMalloc(&ctx->h_tables, want);
+    if (e != hipSuccess) {
+      ctx->h_tables = nullptr;
+      (void)hipGetLastError();
+      return set_error(FPCA_ERR_WORKSPACE, "pinned staging of %zu bytes failed: %s", want, hipGetErrorString(e));
+    }
+    ctx->h_tables_size = want;
+  }
+  *out = static_cast<char *>(ctx->h_tables);
+  return FPCA_OK;
+}
+
 int ws2_reserve(fpca_context *ctx, size_t bytes) { return arena_reserve(ctx, &ctx->ws2, &ctx->ws2_size, bytes); }
 int ws3_reserve(fpca_context *ctx, size_t bytes) { return arena_reserve(ctx, &ctx->ws3, &ctx->ws3_size, bytes); }
 
@@ -188,6 +209,8 @@ int fpca_destroy(fpca_handle ctx) {
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->h_tables) (void)hipHostFree(ctx->h_tables);
+  if (ctx->ev_tables) (void)hipEventDestroy(ctx->ev_tables);
   delete ctx;
   return FPCA_OK;
 }
@@ -208,6 +231,8 @@ int fpca_sync(fpca_handle ctx) {
     *ctx->h_flags = 0;
     FPCA_HIP(hipMemsetAsync(ctx->d_flags, 0, sizeof(int), ctx->stream));
     FPCA_HIP(hipStreamSynchronize(ctx->stream));
+    if (flags & 2)
+      return set_error(FPCA_ERR_DEVICE, "a task of the persistent smoother waited past its spin limit");
     if (flags & 1) return set_error(FPCA_ERR_DOMAIN, "an observation lies outside [0,1]^d or is NaN");
   }
   return FPCA_OK;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "tiled.hpp"
 #include "wls.hpp"
 
 namespace fpca {
@@ -363,6 +364,33 @@ int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double
     if (!C && smooth_cov_fused_d2_supported(grid, bw))
       return smooth_cov_fused_d2(ctx, grid, c_uniform, G, bw, mu, gamma, status);
   }
+  if (tiled_supported(grid)) {
+    // the persistent-queue engine: FP64 moments kept on chip between passes
+    std::vector<TiledJob> jobs(1);
+    TiledJob &j = jobs[0];
+    j = TiledJob{};
+    j.grid = grid;
+    j.Ca = C;
+    j.Ga = G;
+    j.c0 = c_uniform;
+    j.h = bw;
+    j.out = gamma;
+    j.status = status;
+    TiledConfig cfg;
+    size_t lds = tiled_lds(jobs, 16);
+    cfg.qb = 16;
+    if (!lds || lds > 80 * 1024) {
+      cfg.qb = 8;
+      lds = tiled_lds(jobs, 8);
+    }
+    if (lds) {
+      cfg.wg_per_cu = int(std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / (lds + 256))));
+      TiledLaunch L;
+      if (int rc = tiled_plan<T>(ctx, jobs, false, cfg, &L)) return rc;
+      if (int rc = tiled_queue(ctx, L)) return rc;
+      return assemble<T>(ctx, P, gamma, mu, grid->mask);
+    }
+  }
   int dims[MAXD];
   double h[MAXD];
   for (int k = 0; k < d; ++k) {
@@ -371,15 +399,13 @@ int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double
   }
   if (!C) {
     // complete common grid: the pair weights c_uniform (1 - delta_pq) are
-    // materialized for the general engine
-    T *tmp = nullptr;
-    FPCA_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), sizeof(T) * P * P, ctx->stream));
+    // materialized for the general engine, in the handle's second arena
+    if (int rc = ws2_reserve(ctx, carve_bytes(size_t(P) * P, sizeof(T)))) return rc;
+    T *tmp = static_cast<T *>(ctx->ws2);
     hipLaunchKernelGGL(k_offdiag_fill<T>, dim3(nblk(P * P) > 65536 ? 65536 : nblk(P * P)), dim3(256), 0,
                        ctx->stream, tmp, P, T(c_uniform));
     FPCA_LAUNCH_CHECK("offdiag");
-    int rc = smooth_generic<T>(ctx, 2 * d, dims, h, tmp, G, gamma, status);
-    (void)hipFreeAsync(tmp, ctx->stream);
-    if (rc) return rc;
+    if (int rc = smooth_generic<T>(ctx, 2 * d, dims, h, tmp, G, gamma, status)) return rc;
   } else {
     if (int rc = smooth_generic<T>(ctx, 2 * d, dims, h, C, G, gamma, status)) return rc;
   }

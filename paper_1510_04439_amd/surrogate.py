@@ -79,25 +79,14 @@ def features(h: B.Handle, bd: Binned, out=None):
 
 def cv_scores(h: B.Handle, bd: Binned, hs) -> np.ndarray:
     """CV(h) summed over folds for each bandwidth in hs."""
-    sc = B.fpca_cv_batched(h, bd.grid, B.FPCA_F32, N_FOLDS, bd.C, bd.G, bd.Q, np.asarray(hs, np.float64))
-    return sc.sum(axis=1)
+    sc = B.fpca_cv_batched(h, B.FPCA_F32, [(bd.grid, bd.C, bd.G, bd.Q)], N_FOLDS, np.asarray(hs, np.float64))
+    return sc[0].sum(axis=1)
 
 
 def refine_argmin(hs, scores) -> float:
     """Grid argmin of the CV curve, refined by the vertex of the parabola
-    through the three neighbouring points in log h (interior minima only)."""
-    i = int(np.argmin(scores))
-    if i == 0 or i == len(hs) - 1:
-        return float(hs[i])
-    x = np.log(np.asarray(hs[i - 1:i + 2], np.float64))
-    f = np.asarray(scores[i - 1:i + 2], np.float64)
-    den = (x[0] - x[1]) * (x[0] - x[2]) * (x[1] - x[2])
-    a = (x[2] * (f[1] - f[0]) + x[1] * (f[0] - f[2]) + x[0] * (f[2] - f[1])) / den
-    b = (x[2] ** 2 * (f[0] - f[1]) + x[1] ** 2 * (f[2] - f[0]) + x[0] ** 2 * (f[1] - f[2])) / den
-    if not a > 0:
-        return float(hs[i])
-    xv = -b / (2 * a)
-    return float(np.exp(np.clip(xv, x[0], x[2])))
+    through the three neighbouring points in log h (fpca_cv_select)."""
+    return float(B.fpca_cv_select(np.asarray(hs, np.float64), np.asarray(scores, np.float64), 1)[0])
 
 
 class Surrogate:

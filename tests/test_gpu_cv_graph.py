@@ -47,13 +47,13 @@ def test_cv_graph_replays_match_eager(torch, F, M, hs):
     refs = {}
     for name, X in (("A", A), ("B", Bs)):
         he = F.Handle(0)
-        refs[name] = F.fpca_cv_batched(he, g, F.FPCA_F32, nf, *X, hs)
+        refs[name] = F.fpca_cv_batched(he, F.FPCA_F32, [(g, *X)], nf, hs)[0]
         he.close()
     h = F.Handle(0)
     seq = ["A", "B", "A", "B", "B", "A"]  # eager, capture, replays
     for i, name in enumerate(seq):
         X = A if name == "A" else Bs
-        got = F.fpca_cv_batched(h, g, F.FPCA_F32, nf, *X, hs)
+        got = F.fpca_cv_batched(h, F.FPCA_F32, [(g, *X)], nf, hs)[0]
         assert np.array_equal(got, refs[name]), (i, name, got, refs[name])
         # unrelated eager work on the same stream between replays
         tmp = torch.empty(int(np.prod(M)), dtype=torch.float32, device="cuda:0")

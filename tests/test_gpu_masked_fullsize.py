@@ -141,7 +141,7 @@ def test_cv_batched_masked(torch, F, h, M, nf, hs):
     slabs = [oracle.bin_cov_pairs(M, off, t64, y64, folds, fs, want_Q=True) for fs in [-1] + list(range(nf))]
     Ch, Gh, Qh = (np.stack([s[i] for s in slabs]).astype(np.float32).astype(np.float64) for i in range(3))
     C, G, Q = (dev(torch, a.astype(np.float32)) for a in (Ch, Gh, Qh))
-    scores = F.fpca_cv_batched(h, F.Grid(M, dev(torch, mask)), F.FPCA_F32, nf, C, G, Q, hs)
+    scores = F.fpca_cv_batched(h, F.FPCA_F32, [(F.Grid(M, dev(torch, mask)), C, G, Q)], nf, hs)[0]
     ref = np.zeros((len(hs), nf))
     for i, hb in enumerate(hs):
         for f in range(nf):
@@ -292,7 +292,7 @@ def test_c4_full_size_cv_job(torch, F, h, c4_binned):
     P = int(np.prod(ds.M_cov))
     hs = [float(ds.h_grid[0]), float(ds.h_grid[-1])]
     _say(f"c4 full size: batched CV h={hs}")
-    scores = F.fpca_cv_batched(h, grid, F.FPCA_F32, ds.n_folds, C, G, Q, hs)
+    scores = F.fpca_cv_batched(h, F.FPCA_F32, [(grid, C, G, Q)], ds.n_folds, hs)[0]
     assert scores.shape == (2, ds.n_folds) and np.all(np.isfinite(scores))
     for i, f in ((0, 0), (1, 3)):
         W = (C[0] - C[f + 1]).contiguous()

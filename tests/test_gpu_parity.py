@@ -416,7 +416,7 @@ def test_cv_batched_parity(torch, F, h, M, nf, hs):
     slabs = [oracle.bin_cov_pairs(M, off, t64, y64, folds, fs, want_Q=True) for fs in [-1] + list(range(nf))]
     Ch, Gh, Qh = (np.stack([s[i] for s in slabs]).astype(np.float32).astype(np.float64) for i in range(3))
     C, G, Q = (dev(torch, a.astype(np.float32)) for a in (Ch, Gh, Qh))
-    scores = F.fpca_cv_batched(h, F.Grid(M), F.FPCA_F32, nf, C, G, Q, hs)
+    scores = F.fpca_cv_batched(h, F.FPCA_F32, [(F.Grid(M), C, G, Q)], nf, hs)[0]
     ref = np.zeros((len(hs), nf))
     for i, hb in enumerate(hs):
         for f in range(nf):
