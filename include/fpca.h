@@ -329,6 +329,50 @@ int fpca_cv_batched(fpca_handle handle, int dtype, int n_data, const fpca_cv_dat
 int fpca_cv_select(int n_h, int d, const double *bandwidths, const double *cv, double *h_out);
 
 /*
+ * fpca_cv_loo -- the bandwidth criterion of Section 3.3: leave-one-observation-
+ * out cross-validation of the covariance smoother, read on binned data as
+ * leave-one-bin-out. For every bandwidth row h, at every node x of the
+ * 2d-dimensional grid the local-linear fit of eq. 2.4 is computed with x's own
+ * bin left out (its pair weight and sum leave S0 and T0; the other moments are
+ * unchanged because u = 0 there), b_{-x}(x), and
+ *   scores[h] = sum_x Q(x) - 2 G(x) b_{-x}(x) + C(x) b_{-x}(x)^2
+ * with b_{-x} = 0 where the reduced window is empty or x lies outside the
+ * mask (= sum over pairs of w (Y_ij Y_il - b)^2 spread over their bins; it is
+ * exactly leave-one-observation-out CV when every bin holds one pair on its
+ * node). FP64 moments and solves, FP64 sum. One persistent launch per call.
+ *   C, G, Q: P x P device arrays of `dtype` (fpca_bin kind COV with sq_sums,
+ *     without folds). bandwidths: host, n_h x d. scores: host, n_h.
+ * Grids: P <= 4096 and M_1 <= 64 (d = 1), 32 (d = 2), 16 (d = 3); otherwise
+ * FPCA_ERR_UNSUPPORTED. Synchronizes.
+ */
+int fpca_cv_loo(fpca_handle handle, const fpca_grid *grid, int dtype, const void *C, const void *G, const void *Q,
+                int n_h, const double *bandwidths, double *scores);
+
+/*
+ * fpca_bw_search -- the bandwidth search of Section 3.3: fpca_cv_loo minimized
+ * over continuous per-coordinate bandwidths (the s- and t-coordinates share
+ * them) by a derivative-free trust-region method in log h whose local model is
+ * a quadratic least-squares regression on the sampled criterion (the paper's
+ * replacement of the interpolation step, the criterion being noisy).
+ * Initial radius 0.25 x the widest side of the log box (within [0.05, 1]);
+ * initial design: the start, +-r e_k, +-r/2 e_k, start + r/2 (e_k + e_l);
+ * model fitted to the samples within 2r (max norm) of the centre, or to the
+ * (d+1)(d+2)/2 + 1 nearest; the step minimizes the model in the ball of
+ * radius r; accepted when the actual/predicted decrease is at least 0.1
+ * (radius doubled at 0.75 when the step reaches 0.9 r), else the radius is
+ * halved and a geometry sample centre + r e_k is added; stop when r < 0.01 or
+ * after max_evals criteria. Candidates are clipped to [h_lo, h_hi]; the best
+ * sample wins. Each iteration's 1-2 criteria are one launch.
+ *   h_lo, h_hi, h_init: host, d each (0 < h_lo <= h_hi). max_evals >= the
+ *   initial design (1 + 4d + d(d-1)/2). h_out: host, d. cv_out, n_evals:
+ *   host, or NULL. trace: host, max_evals x (d + 1) (h and criterion of every
+ *   sample in order), or NULL. Synchronizes.
+ */
+int fpca_bw_search(fpca_handle handle, const fpca_grid *grid, int dtype, const void *C, const void *G,
+                   const void *Q, const double *h_lo, const double *h_hi, const double *h_init, int max_evals,
+                   double *h_out, double *cv_out, int *n_evals, double *trace);
+
+/*
  * Bandwidth surrogate (an addition to the paper's method, whose Section 3.3
  * selects bandwidths by CV with a trust-region search): a small MLP maps 32
  * summary features of the binned arrays to log h of the covariance smoother.

@@ -13,7 +13,9 @@ Each function names the passage of the paper it follows:
   - noise variance: eq. (2.6), from the smooth of eq. (2.5);
   - principal component scores: eq. (2.7); reconstruction after it;
   - matrixization and rescaling: Section 3.1, eq. (3.1);
-  - random projection: Section 3.4.
+  - random projection: Section 3.4;
+  - bandwidth search (leave-one-out CV by a trust region with a quadratic
+    regression model): Section 3.3, in `oracle/bw_search.py`.
 """
 from __future__ import annotations
 

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
-    "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select",
+    "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
 ]
 
 
@@ -86,6 +86,10 @@ def load_library(path: str = LIB_PATH):
     L.fpca_rng_normal.argtypes = [vp, u64, i64, vp]
     L.fpca_cv_batched.argtypes = [vp, i32, i32, ctypes.POINTER(_CvDataC), i32, i32,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.fpca_cv_loo.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, i32, dp, dp]
+    L.fpca_bw_search.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, vp, dp, dp, dp, i32, dp, dp,
+                                 ctypes.POINTER(i32), dp]
     L.fpca_cv_select.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
     L.fpca_bw_features.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -308,3 +312,32 @@ def fpca_cv_select(bandwidths, cv, d: int = 1) -> np.ndarray:
     _check(load_library().fpca_cv_select(bw.shape[0], d, bw.ctypes.data_as(P), cvv.ctypes.data_as(P),
                                          out.ctypes.data_as(P)))
     return out
+
+
+def fpca_cv_loo(h: Handle, grid: Grid, dtype: int, C, G, Q, bandwidths) -> np.ndarray:
+    """Leave-one-out criteria (n_h) of the bandwidth rows (n_h x d, or n_h scalars)."""
+    bw = _bw_rows(bandwidths, grid.d)
+    out = np.zeros(bw.shape[0])
+    g = grid.c()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().fpca_cv_loo(h.ptr, ctypes.byref(g), int(dtype), _ptr(C), _ptr(G), _ptr(Q), bw.shape[0],
+                                      bw.ctypes.data_as(P), out.ctypes.data_as(P)))
+    return out
+
+
+def fpca_bw_search(h: Handle, grid: Grid, dtype: int, C, G, Q, h_lo, h_hi, h_init, max_evals: int = 40):
+    """Trust-region bandwidth search; returns (h (d), criterion, evaluations, trace (n x (d+1)))."""
+    d = grid.d
+    arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (d,)))
+    lo, hi, h0 = arr(h_lo), arr(h_hi), arr(h_init)
+    hout = np.zeros(d)
+    cv = np.zeros(1)
+    n = ctypes.c_int(0)
+    trace = np.zeros((max_evals, d + 1))
+    g = grid.c()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().fpca_bw_search(h.ptr, ctypes.byref(g), int(dtype), _ptr(C), _ptr(G), _ptr(Q),
+                                         lo.ctypes.data_as(P), hi.ctypes.data_as(P), h0.ctypes.data_as(P),
+                                         int(max_evals), hout.ctypes.data_as(P), cv.ctypes.data_as(P),
+                                         ctypes.byref(n), trace.ctypes.data_as(P)))
+    return hout, float(cv[0]), int(n.value), trace[:min(n.value, max_evals)]

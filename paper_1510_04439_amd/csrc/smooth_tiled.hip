@@ -405,8 +405,18 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
 #pragma unroll
       for (int i = 0; i < NM; ++i) m[i] = F[((long long)i * M1 + a1) * QB + c];
       int8_t st;
-      const double b0 = wls_b0<D>(m, &st);
       const long long o = ((long long)a1 * PR + r) * P + q0 + c;
+      if (jb.loo) {
+        // the node's own bin: u = 0 there, so it enters S0 and T0 only
+        const T *Ca = static_cast<const T *>(jb.Ca), *Cb = static_cast<const T *>(jb.Cb);
+        const T *Ga = static_cast<const T *>(jb.Ga), *Gb = static_cast<const T *>(jb.Gb);
+        const double cw = Ca ? double(Ca[o]) - (Cb ? double(Cb[o]) : 0.0)
+                             : (a1 * PR + r == q0 + c ? 0.0 : jb.c0);
+        const double gw = double(Ga[o]) - (Gb ? double(Gb[o]) : 0.0);
+        m[0] -= cw;
+        m[1 + D + D * (D + 1) / 2] -= gw;
+      }
+      const double b0 = wls_b0<D>(m, &st);
       if (a.cv) {
         static_cast<T *>(slot_g(a, jb.slot))[o] = T(b0);
       } else {
@@ -419,7 +429,8 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
 
 // ------------------------------------------------------------------ score
 // Tile pairs (I, J), I <= J, of the P x P grid in TQ_TILE x TQ_TILE tiles; g is b0
-// symmetrized, 0 outside the mask and where b0 is NaN (an empty window).
+// symmetrized (for leave-one-out jobs the node's own b0), 0 outside the mask
+// and where b0 is NaN (an empty window).
 template <typename T>
 __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, LDbl *lds) {
   const int P = jb.P;
@@ -482,7 +493,8 @@ __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, L
       // (p, q) in tile (I, J): g = (b(p,q) + b(q,p)) / 2 = (A[rr][cc] + B[cc][rr]) / 2
       if (in1[u]) {
         const int p = r0 + rr, q = c0 + cc;
-        double g = 0.5 * (A[rr * (TQ_TILE + 1) + cc] + B[cc * (TQ_TILE + 1) + rr]);
+        double g = jb.loo ? A[rr * (TQ_TILE + 1) + cc]
+                          : 0.5 * (A[rr * (TQ_TILE + 1) + cc] + B[cc * (TQ_TILE + 1) + rr]);
         if (mask && (!mask[p] || !mask[q])) g = 0.0;
         if (g != g) g = 0.0;
         s += q1[u] - 2.0 * g1[u] * g + w1[u] * g * g;
@@ -490,7 +502,8 @@ __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, L
       // (q, p) = (c0 + rr, r0 + cc): g = (B[rr][cc] + A[cc][rr]) / 2
       if (in2[u]) {
         const int q = c0 + rr, p = r0 + cc;
-        double g = 0.5 * (B[rr * (TQ_TILE + 1) + cc] + A[cc * (TQ_TILE + 1) + rr]);
+        double g = jb.loo ? B[rr * (TQ_TILE + 1) + cc]
+                          : 0.5 * (B[rr * (TQ_TILE + 1) + cc] + A[cc * (TQ_TILE + 1) + rr]);
         if (mask && (!mask[p] || !mask[q])) g = 0.0;
         if (g != g) g = 0.0;
         s += q2[u] - 2.0 * g2[u] * g + w2[u] * g * g;
@@ -757,6 +770,7 @@ int tiled_plan(fpca_context *ctx, const std::vector<TiledJob> &jobs, bool cv, co
     t.Cf = jobs[j].Cf;
     t.mask = g->mask;
     t.c0 = jobs[j].c0;
+    t.loo = jobs[j].loo;
     t.out = jobs[j].out;
     t.status = jobs[j].status;
     int P = 1;

@@ -23,6 +23,7 @@ struct TJob {
   const void *Qf, *Gf, *Cf;       // cross-validation: the held-out fold's slabs
   const uint8_t *mask;
   double c0;                      // Ca == null: C = c0 off the diagonal, 0 on it (complete common grid)
+  int loo;                        // leave each node's own bin out of its fit (leave-one-out CV)
   void *out;                      // smooth mode: b0, P x P of T
   int8_t *status;                 // smooth mode: optional status
   double h[3];
@@ -78,6 +79,7 @@ struct TiledJob {
   const fpca_grid *grid;
   const void *Ca, *Cb, *Ga, *Gb, *Qf, *Gf, *Cf;
   double c0;  // used when Ca is null
+  int loo;    // leave-one-bin-out fit and unsymmetrized score
   const double *h;  // d bandwidths
   void *out;
   int8_t *status;
