@@ -156,6 +156,25 @@ int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const
                      int8_t *status);
 
 /*
+ * fpca_set_conv -- how the general smoother (fpca_smooth_mean, and
+ * fpca_smooth_cov on grids the task-queue smoother does not take) forms its
+ * 1-D moment passes: FPCA_CONV_DIRECT sums the 2R+1 taps per output
+ * (default); FPCA_CONV_FFT uses the FFT strategy of Section 3.2 on binned data
+ * (per line of the pass, the zero-padded line and the taps are transformed
+ * with L >= M + R points, L a power of two up to 4096, multiplied and
+ * transformed back; passes with M + R > 4096 stay direct); FPCA_CONV_AUTO
+ * times both the first time a pass shape is met on this handle and keeps the
+ * faster (no timing while the stream is being captured: direct then).
+ * The FFT pass agrees with the direct one to FP64 rounding relative to the
+ * largest value of the line; values below 1e-12 of (max |line| x sum |taps|)
+ * are set to 0, which keeps empty windows empty.
+ */
+#define FPCA_CONV_DIRECT 0
+#define FPCA_CONV_FFT 1
+#define FPCA_CONV_AUTO 2
+int fpca_set_conv(fpca_handle handle, int mode);
+
+/*
  * fpca_smooth_cov -- the covariance (eq. 2.4): the same smoother on the
  * 2d-dimensional grid of (s, t) pairs, applied to the pair weights C and raw
  * products G from fpca_bin kind COV (slab 0), giving b0(s,t), then

@@ -27,6 +27,7 @@ FPCA_IRREGULAR, FPCA_COMMON_GRID = 0, 1
 FPCA_F64, FPCA_F32 = 0, 1
 FPCA_PREC_F64, FPCA_PREC_F32, FPCA_PREC_BF16X3 = 0, 1, 2
 FPCA_K_EPANECHNIKOV = 0
+FPCA_CONV_DIRECT, FPCA_CONV_FFT, FPCA_CONV_AUTO = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
@@ -34,6 +35,7 @@ EXPORTED_SYMBOLS = [
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
     "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
+    "fpca_set_conv",
 ]
 
 
@@ -67,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     L.fpca_destroy.argtypes = [vp]
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
+    L.fpca_set_conv.argtypes = [vp, i32]
     L.fpca_reconstruct.argtypes = [vp, i32, i64, i64, i32, vp, vp, vp, vp]
     L.fpca_pace_scores.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
@@ -341,3 +344,8 @@ def fpca_bw_search(h: Handle, grid: Grid, dtype: int, C, G, Q, h_lo, h_hi, h_ini
                                          int(max_evals), hout.ctypes.data_as(P), cv.ctypes.data_as(P),
                                          ctypes.byref(n), trace.ctypes.data_as(P)))
     return hout, float(cv[0]), int(n.value), trace[:min(n.value, max_evals)]
+
+
+def fpca_set_conv(h: Handle, mode: int):
+    """Pass method of the general smoother: FPCA_CONV_DIRECT, FPCA_CONV_FFT or FPCA_CONV_AUTO."""
+    _check(load_library().fpca_set_conv(h.ptr, int(mode)))

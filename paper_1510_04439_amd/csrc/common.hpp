@@ -43,6 +43,10 @@ struct fpca_context {
   void *h_tables = nullptr;
   size_t h_tables_size = 0;
   hipEvent_t ev_tables = nullptr;
+  // Pass method of the general smoother (FPCA_CONV_*), and the choices AUTO
+  // has timed, per pass shape.
+  int conv_mode = FPCA_CONV_DIRECT;
+  std::vector<std::pair<std::vector<int64_t>, int>> conv_cache;
   // Tile shapes chosen by the autotuner, per batched-CV shape key.
   std::vector<std::pair<std::vector<double>, std::pair<int, int>>> tune_cache;
 };

@@ -92,6 +92,148 @@ struct MomPtrs {
   const double *p[MAXMOM];
 };
 
+// ---------------------------------------------------------------- FFT passes
+// The same pass by the convolution theorem, for long windows: along a line of
+// M values, out_j(o) = sum_m taps_j[m] in(o + m) is the cross-correlation of
+// the zero-padded line with the taps, i.e. the inverse FFT of
+// FFT(line) * conj(FFT(taps placed circularly)) with L >= M + R (a power of two,
+// so the wrap-around never reaches the kept outputs). FP64 complex radix-2 FFTs
+// in LDS (one workgroup per line and array); the tap spectra and twiddles are
+// formed once per pass. Values below 1e-12 x (max |line| x sum |taps_j|) are
+// flushed to zero: they are rounding residue of sums that are exactly zero in
+// the direct pass (an empty window keeps S0 = 0 and its EMPTY status).
+constexpr int FFT_LMAX = 4096;
+constexpr int FFT_T = 256;
+
+__device__ inline int bitrev(int x, int logL) { return int(__brev(unsigned(x)) >> (32 - logL)); }
+
+// In-place radix-2 transforms of nl lines of length L stored one after the
+// other in buf (input in bit-reversed order, output in natural order);
+// tw[k] = exp(-2 pi i k / L), conjugated for the inverse.
+__device__ void fft_lds(double2 *buf, int L, int logL, int nl, const double2 *tw, bool inverse) {
+  const int nb = nl * (L / 2);
+  for (int s = 1; s <= logL; ++s) {
+    const int half = 1 << (s - 1);
+    const int tstep = L >> s;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int l = b >> (logL - 1), bb = b & (L / 2 - 1);
+      const int grp = bb >> (s - 1), j = bb & (half - 1);
+      const int i0 = l * L + grp * (half << 1) + j, i1 = i0 + half;
+      double2 w = tw[j * tstep];
+      if (inverse) w.y = -w.y;
+      const double2 u = buf[i0], v0 = buf[i1];
+      const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+}
+
+// Per pass: twiddles (block 0) and, per tap family e (block e), conj(FFT(taps_e
+// placed at m mod L)) and sum |taps_e|.
+__global__ __launch_bounds__(FFT_T) void k_fft_setup(int L, int logL, int R, const double *__restrict__ taps,
+                                                   double2 *__restrict__ tw, double2 *__restrict__ spec,
+                                                   double *__restrict__ tapsum) {
+  extern __shared__ double2 sm[];
+  double2 *buf = sm;      // [L]
+  double2 *twl = sm + L;  // [L/2]
+  const int e = blockIdx.x, W = 2 * R + 1;
+  for (int k = threadIdx.x; k < L / 2; k += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * double(k) / double(L), &sn, &cs);
+    twl[k] = make_double2(cs, sn);
+    if (e == 0) tw[k] = twl[k];
+  }
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    const int m = i <= R ? i : i - L;  // circular position of offset m
+    const double v = (m >= -R && m <= R) ? taps[e * W + m + R] : 0.0;
+    buf[bitrev(i, logL)] = make_double2(v, 0.0);
+  }
+  __syncthreads();
+  fft_lds(buf, L, logL, 1, twl, false);
+  for (int k = threadIdx.x; k < L; k += blockDim.x) spec[e * L + k] = make_double2(buf[k].x, -buf[k].y);
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int m = 0; m < W; ++m) s += fabs(taps[e * W + m]);
+    tapsum[e] = s;
+  }
+}
+
+// Two real lines share one complex transform: line 2i is the real part and
+// line 2i+1 the imaginary part. Correlating with real taps is a real-linear
+// map, so the inverse transform of (spectrum x tap spectrum) returns line
+// 2i's correlation in its real part and line 2i+1's in its imaginary part.
+// One workgroup takes npair = FFT_BATCH / L such pairs (L >= 16). Element
+// (line l, position x) maps to thread slots so that neighbouring threads
+// touch neighbouring addresses: x fastest along the contiguous coordinate
+// (stride 1), the line fastest along the others (neighbouring lines are
+// neighbours in memory there).
+constexpr int FFT_BATCH = 2048;
+constexpr int FFT_LMIN = 16;
+
+template <typename TS>
+__global__ __launch_bounds__(FFT_T) void k_pass_fft(int64_t stride, int Mk, int64_t nlines, int L, int logL,
+                                                  int npair, PassBatch<TS> pb, const double2 *__restrict__ tw,
+                                                  const double2 *__restrict__ spec,
+                                                  const double *__restrict__ tapsum) {
+  extern __shared__ double2 sm[];
+  double2 *A = sm;              // [npair][L]: transform of each pair of lines
+  double2 *Bf = sm + npair * L;  // [npair][L]: one family's product, then its correlation
+  __shared__ unsigned long long amax_l[2 * FFT_BATCH / FFT_LMIN];
+  const int a = blockIdx.y;
+  const int nl = 2 * npair;
+  const int64_t line0 = int64_t(blockIdx.x) * nl;
+  const TS *__restrict__ src = pb.src[a];
+  const int nj = pb.nj[a];
+  const int E = nl * L;
+  const bool xfast = stride == 1;
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) amax_l[l] = 0ull;
+  __syncthreads();
+  for (int i = threadIdx.x; i < E; i += blockDim.x) {
+    const int l = xfast ? i >> logL : i % nl;
+    const int x = xfast ? i & (L - 1) : i / nl;
+    const int64_t line = line0 + l;
+    double v = 0.0;
+    if (x < Mk && line < nlines) {
+      const int64_t base = (line / stride) * (stride * Mk) + line % stride;
+      v = double(src[base + int64_t(x) * stride]);
+    }
+    // non-negative doubles order as their bit patterns
+    if (v != 0.0) atomicMax(&amax_l[l], static_cast<unsigned long long>(__double_as_longlong(fabs(v))));
+    double *slot = reinterpret_cast<double *>(&A[(l >> 1) * L + bitrev(x, logL)]);
+    slot[l & 1] = v;
+  }
+  __syncthreads();
+  fft_lds(A, L, logL, npair, tw, false);
+  const double inv = 1.0 / double(L);
+  const int Ep = npair * L;
+  for (int j = 0; j < nj; ++j) {
+    for (int i = threadIdx.x; i < Ep; i += blockDim.x) {
+      const int k = i & (L - 1);
+      const double2 x = A[i], y = spec[j * L + k];
+      Bf[(i & ~(L - 1)) + bitrev(k, logL)] = make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+    }
+    __syncthreads();
+    fft_lds(Bf, L, logL, npair, tw, true);
+    const double ts = 1e-12 * tapsum[j];
+    double *__restrict__ out = pb.out[a][j];
+    for (int i = threadIdx.x; i < E; i += blockDim.x) {
+      const int l = xfast ? i >> logL : i % nl;
+      const int x = xfast ? i & (L - 1) : i / nl;
+      const int64_t line = line0 + l;
+      if (x < Mk && line < nlines) {
+        const int64_t base = (line / stride) * (stride * Mk) + line % stride;
+        const double2 c = Bf[(l >> 1) * L + x];
+        const double v = ((l & 1) ? c.y : c.x) * inv;
+        const double thr = ts * __longlong_as_double(static_cast<long long>(amax_l[l]));
+        out[base + int64_t(x) * stride] = fabs(v) <= thr ? 0.0 : v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -227,11 +369,15 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
   const size_t bytesA = carve_bytes(maxA * size_t(total), sizeof(double));
   const size_t bytesB = carve_bytes(maxB * size_t(total), sizeof(double));
   const size_t bytesT = carve_bytes(tap_count, sizeof(double));
-  if (int rc = ws_reserve(ctx, bytesA + bytesB + bytesT)) return rc;
+  const size_t bytesF = carve_bytes(FFT_LMAX / 2 + 3 * FFT_LMAX, sizeof(double2)) + carve_bytes(3, sizeof(double));
+  if (int rc = ws_reserve(ctx, bytesA + bytesB + bytesT + bytesF)) return rc;
   Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
   double *bufA = cv.take<double>(maxA * size_t(total));
   double *bufB = cv.take<double>(maxB * size_t(total));
   double *taps = cv.take<double>(tap_count);
+  double2 *f_tw = cv.take<double2>(FFT_LMAX / 2);
+  double2 *f_spec = cv.take<double2>(3 * FFT_LMAX);
+  double *f_sum = cv.take<double>(3);
   // tap tables are computed on the device (no host buffer in the stream: the
   // sequence can be captured into a graph)
   {
@@ -274,13 +420,79 @@ int smooth_generic(fpca_context *ctx, int D, const int *dims, const double *h, c
         b1.src[a] = cur[a];
       o += nj;
     }
-    if (s == 0)
-      hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total, stride[k],
-                         dims[k], b0, taps + tap_off[k], R[k]);
-    else
-      hipLaunchKernelGGL(k_pass<double>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total,
-                         stride[k], dims[k], b1, taps + tap_off[k], R[k]);
-    FPCA_LAUNCH_CHECK("moment pass");
+    // direct or FFT pass (the handle's convolution mode; AUTO times both the
+    // first time a pass shape is met and keeps the faster)
+    int L = FFT_LMIN, logL = 4;
+    while (L < dims[k] + R[k]) {
+      L <<= 1;
+      ++logL;
+    }
+    const bool fft_ok = L <= FFT_LMAX && total / dims[k] <= 0x7fffffffLL;
+    auto run_direct = [&]() -> int {
+      if (s == 0)
+        hipLaunchKernelGGL(k_pass<T>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total, stride[k],
+                           dims[k], b0, taps + tap_off[k], R[k]);
+      else
+        hipLaunchKernelGGL(k_pass<double>, dim3(nblk(total), unsigned(na)), dim3(256), 0, ctx->stream, total,
+                           stride[k], dims[k], b1, taps + tap_off[k], R[k]);
+      FPCA_LAUNCH_CHECK("moment pass");
+      return FPCA_OK;
+    };
+    auto run_fft = [&]() -> int {
+      // up to 96 KB (setup) and 128 KB (pass) of dynamic LDS at L = 4096
+      FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_setup),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, FFT_LMAX * 24));
+      FPCA_HIP(hipFuncSetAttribute(s == 0 ? reinterpret_cast<const void *>(&k_pass_fft<T>)
+                                          : reinterpret_cast<const void *>(&k_pass_fft<double>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, FFT_LMAX * 32));
+      hipLaunchKernelGGL(k_fft_setup, dim3(3), dim3(FFT_T), size_t(L) * 24, ctx->stream, L, logL, R[k],
+                         taps + tap_off[k], f_tw, f_spec, f_sum);
+      FPCA_LAUNCH_CHECK("fft setup");
+      const int64_t nlines = total / dims[k];
+      const int npair = std::max(1, FFT_BATCH / L);
+      const dim3 grid(unsigned((nlines + 2 * npair - 1) / (2 * npair)), unsigned(na));
+      const size_t lds = size_t(npair) * L * 32;
+      if (s == 0)
+        hipLaunchKernelGGL(k_pass_fft<T>, grid, dim3(FFT_T), lds, ctx->stream, stride[k], dims[k], nlines, L, logL,
+                           npair, b0, f_tw, f_spec, f_sum);
+      else
+        hipLaunchKernelGGL(k_pass_fft<double>, grid, dim3(FFT_T), lds, ctx->stream, stride[k], dims[k], nlines, L,
+                           logL, npair, b1, f_tw, f_spec, f_sum);
+      FPCA_LAUNCH_CHECK("fft pass");
+      return FPCA_OK;
+    };
+    int method = 0;  // 0 direct, 1 FFT
+    if (fft_ok && ctx->conv_mode == FPCA_CONV_FFT) method = 1;
+    if (fft_ok && ctx->conv_mode == FPCA_CONV_AUTO) {
+      const std::vector<int64_t> key = {int64_t(s == 0 ? sizeof(T) : 8), total, stride[k], dims[k], R[k], na};
+      int found = -1;
+      for (const auto &e : ctx->conv_cache)
+        if (e.first == key) found = e.second;
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      (void)hipStreamIsCapturing(ctx->stream, &cs);
+      if (found < 0 && cs == hipStreamCaptureStatusNone) {
+        hipEvent_t e0, e1, e2;
+        FPCA_HIP(hipEventCreate(&e0));
+        FPCA_HIP(hipEventCreate(&e1));
+        FPCA_HIP(hipEventCreate(&e2));
+        FPCA_HIP(hipEventRecord(e0, ctx->stream));
+        if (int rc = run_fft()) return rc;
+        FPCA_HIP(hipEventRecord(e1, ctx->stream));
+        if (int rc = run_direct()) return rc;
+        FPCA_HIP(hipEventRecord(e2, ctx->stream));
+        FPCA_HIP(hipEventSynchronize(e2));
+        float t_fft = 0.f, t_dir = 0.f;
+        FPCA_HIP(hipEventElapsedTime(&t_fft, e0, e1));
+        FPCA_HIP(hipEventElapsedTime(&t_dir, e1, e2));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        found = t_fft < t_dir ? 1 : 0;
+        ctx->conv_cache.push_back({key, found});
+      }
+      method = found > 0 ? 1 : 0;
+    }
+    if (int rc = method == 1 ? run_fft() : run_direct()) return rc;
     cur.swap(next);
   }
   // Gather the final arrays in moment order.
@@ -459,4 +671,12 @@ int fpca::smooth_cov_internal(fpca_context *ctx, const fpca_grid *grid, int dtyp
                                    static_cast<double *>(gamma), status);
   return smooth_cov_impl<float>(ctx, grid, static_cast<const float *>(C), c_uniform, static_cast<const float *>(G),
                                 static_cast<const float *>(mu), bandwidth, static_cast<float *>(gamma), status);
+}
+
+extern "C" int fpca_set_conv(fpca_handle ctx, int mode) {
+  if (int rc = check_handle(ctx)) return rc;
+  if (mode != FPCA_CONV_DIRECT && mode != FPCA_CONV_FFT && mode != FPCA_CONV_AUTO)
+    return set_error(FPCA_ERR_INVALID_ARG, "bad convolution mode %d", mode);
+  ctx->conv_mode = mode;
+  return FPCA_OK;
 }
