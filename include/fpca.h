@@ -231,6 +231,50 @@ int fpca_eig_randomized(fpca_handle handle, int dtype, int prec, const fpca_grid
                         int power_iters, uint64_t seed, double *evals, void *efuns, double *fve);
 
 /*
+ * The smoothed covariance of complete common-grid data as an operator
+ * (Section 3.2's blockwise processing with the products of Section 3.4): the
+ * P x P covariance Gamma_hat of eq. 2.4 (pair weights of the complete design,
+ * the binned local-linear fit, Gamma = b0 - mu mu^T, symmetric to rounding)
+ * is never stored; products Gamma_hat X are formed from the curves. For
+ * covariance nodes whose s- and t-windows share no grid node the fit has a
+ * closed form that factors over s and t, so off the band |s - t| <= 2R (per
+ * coordinate) Gamma_hat has rank <= 2n + 1; on the band every node's
+ * (2d+1)-moment system is solved in FP64 with the diagonal pairs removed.
+ *
+ * fpca_covop_create -- builds the operator.
+ *   grid: d = 1..3, no mask; Y: device, n x P row-major FP64, every curve
+ *     observed at every node (no NaN); mu: device, P FP64 (the smoothed mean,
+ *     e.g. from fpca_smooth_mean), copied; bandwidth: host, d values shared by
+ *     the s- and t-coordinates; each coordinate's window must span 1..R_max
+ *     grid steps (R_max = 2016, 28, 6 for d = 1, 2, 3) and be non-degenerate
+ *     at every node, else FPCA_ERR_UNSUPPORTED.
+ *   mode: FPCA_COVOP_RECOMPUTE (the band is recomputed tile by tile in every
+ *     product; the operator holds O(n P) memory) or FPCA_COVOP_STORE_BAND (the
+ *     band is formed once and kept in 64 x 64 FP64 blocks, about
+ *     P x 64 x prod_k (2 ceil(2R_k / b_k) + 1) doubles with tile extents
+ *     b = 64 / 8 / 4 for d = 1 / 2 / 3; products then stream it).
+ *   The operator allocates its own device memory (FPCA_ERR_WORKSPACE if it
+ *   does not fit), keeps the handle, and uses the handle's stream at each
+ *   call. Synchronizes the stream.
+ * fpca_covop_apply -- out = Gamma_hat X; X, out: device, P x r row-major FP64
+ *   (node-major), 1 <= r <= 64; asynchronous on the handle's stream.
+ * fpca_covop_destroy -- waits for the handle's stream and frees the operator.
+ * fpca_eig_covop -- fpca_eig_randomized (same algorithm, test matrix,
+ *   orthonormalization, rescaling and sign rule, FP64) with every product
+ *   taken through the operator; quad_w NULL means the Riemann weights.
+ *   efuns: device, P x k column-major FP64.
+ */
+typedef struct fpca_covop_s *fpca_covop;
+#define FPCA_COVOP_RECOMPUTE 0
+#define FPCA_COVOP_STORE_BAND 1
+int fpca_covop_create(fpca_handle handle, const fpca_grid *grid, int64_t n, const double *Y, const double *mu,
+                      const double *bandwidth, int mode, fpca_covop *op);
+int fpca_covop_apply(fpca_covop op, int r, const double *X, double *out);
+int fpca_covop_destroy(fpca_covop op);
+int fpca_eig_covop(fpca_covop op, const double *quad_w, int k, int oversample, int power_iters, uint64_t seed,
+                   double *evals, double *efuns, double *fve);
+
+/*
  * fpca_noise_variance -- measurement-error variance (eq. 2.6, from the
  * smooth of eq. 2.5). At every node t of `grid` (P nodes):
  *   sigma2_t[t] = b0[t] - gamma[t, t] - mu[t]^2

@@ -28,6 +28,7 @@ FPCA_F64, FPCA_F32 = 0, 1
 FPCA_PREC_F64, FPCA_PREC_F32, FPCA_PREC_BF16X3 = 0, 1, 2
 FPCA_K_EPANECHNIKOV = 0
 FPCA_CONV_DIRECT, FPCA_CONV_FFT, FPCA_CONV_AUTO = 0, 1, 2
+FPCA_COVOP_RECOMPUTE, FPCA_COVOP_STORE_BAND = 0, 1
 
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
@@ -35,7 +36,7 @@ EXPORTED_SYMBOLS = [
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
     "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
-    "fpca_set_conv",
+    "fpca_set_conv", "fpca_covop_create", "fpca_covop_apply", "fpca_covop_destroy", "fpca_eig_covop",
 ]
 
 
@@ -70,6 +71,12 @@ def load_library(path: str = LIB_PATH):
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
     L.fpca_set_conv.argtypes = [vp, i32]
+    L.fpca_covop_create.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, ctypes.POINTER(ctypes.c_double), i32,
+                                    ctypes.POINTER(vp)]
+    L.fpca_covop_apply.argtypes = [vp, i32, vp, vp]
+    L.fpca_covop_destroy.argtypes = [vp]
+    L.fpca_eig_covop.argtypes = [vp, vp, i32, i32, i32, u64, ctypes.POINTER(ctypes.c_double), vp,
+                                 ctypes.POINTER(ctypes.c_double)]
     L.fpca_reconstruct.argtypes = [vp, i32, i64, i64, i32, vp, vp, vp, vp]
     L.fpca_pace_scores.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
@@ -349,3 +356,36 @@ def fpca_bw_search(h: Handle, grid: Grid, dtype: int, C, G, Q, h_lo, h_hi, h_ini
 def fpca_set_conv(h: Handle, mode: int):
     """Pass method of the general smoother: FPCA_CONV_DIRECT, FPCA_CONV_FFT or FPCA_CONV_AUTO."""
     _check(load_library().fpca_set_conv(h.ptr, int(mode)))
+
+
+class CovOp:
+    """fpca_covop_create / fpca_covop_destroy: the smoothed covariance of
+    complete common-grid curves Y (n x P, FP64 device) as an operator."""
+
+    def __init__(self, h: Handle, grid: Grid, Y, mu, bandwidth, mode: int = FPCA_COVOP_RECOMPUTE):
+        self.h = h
+        self.grid = grid
+        g = grid.c()
+        op = ctypes.c_void_p()
+        _check(load_library().fpca_covop_create(h.ptr, ctypes.byref(g), int(Y.shape[0]), _ptr(Y), _ptr(mu),
+                                                _bw(bandwidth, grid.d), int(mode), ctypes.byref(op)))
+        self._op = op
+
+    def apply(self, X, out):
+        """out = Gamma_hat X for X, out: P x r row-major FP64 device tensors."""
+        self.h.ptr  # binds the current stream to the handle
+        _check(load_library().fpca_covop_apply(self._op, int(X.shape[1]), _ptr(X), _ptr(out)))
+
+    def eig(self, quad_w, k: int, oversample: int, power_iters: int, seed: int, efuns):
+        """fpca_eig_covop; returns (evals[k], fve[k]); efuns: k x P FP64 tensor."""
+        self.h.ptr
+        ev = (ctypes.c_double * k)()
+        fv = (ctypes.c_double * k)()
+        _check(load_library().fpca_eig_covop(self._op, _ptr(quad_w), k, oversample, power_iters,
+                                             ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ev, _ptr(efuns), fv))
+        return np.array(ev[:]), np.array(fv[:])
+
+    def close(self):
+        if self._op:
+            load_library().fpca_covop_destroy(self._op)
+            self._op = None

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libfpca.so")
 SOURCES = ["context.hip", "bin.hip", "gemm.hip", "smooth.hip", "smooth_fused.hip", "eig.hip", "cv.hip", "surrogate.hip",
-           "noise.hip", "pace.hip", "smooth_tiled.hip", "bwsearch.hip"]
+           "noise.hip", "pace.hip", "smooth_tiled.hip", "bwsearch.hip", "covop.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

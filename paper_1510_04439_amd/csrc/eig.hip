@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "covop.hpp"
 
 namespace fpca {
 namespace {
@@ -743,7 +744,7 @@ inline unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
 
 template <typename T, int RP>
 int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k, int r,
-            int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
+            int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h, fpca_covop_s *op) {
   const bool f32 = sizeof(T) == 4;
   // K split of the panel product: enough workgroups to fill the chip
   const int64_t colblocks = (P + 63) / 64;
@@ -800,9 +801,14 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
                            (const float *)X, kchunk, part);
       FPCA_LAUNCH_CHECK("panel_f32");
     } else {
-      hipLaunchKernelGGL(k_panel_f64, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, P, RP, (const double *)gamma,
-                         (const double *)X, Yraw);
-      FPCA_LAUNCH_CHECK("panel_f64");
+      if (op) {
+        // the covariance operator: Gamma X without Gamma
+        if (int rc = covop_apply_internal(op, RP, (const double *)X, Yraw)) return rc;
+      } else {
+        hipLaunchKernelGGL(k_panel_f64, dim3(nb(P * RP)), dim3(256), 0, ctx->stream, P, RP, (const double *)gamma,
+                           (const double *)X, Yraw);
+        FPCA_LAUNCH_CHECK("panel_f64");
+      }
     }
     if (mode == 2)
       hipLaunchKernelGGL((k_rows_gram<2, RP>), dim3(unsigned(ngram)), dim3(RT), 0, ctx->stream, P, int(nsplit), part,
@@ -876,13 +882,14 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
 
 template <typename T>
 int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k,
-             int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h) {
+             int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h,
+             fpca_covop_s *op = nullptr) {
   const int r = k + oversample;
   switch ((r + 15) / 16) {
-    case 1: return eig_run<T, 16>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
-    case 2: return eig_run<T, 32>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
-    case 3: return eig_run<T, 48>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
-    default: return eig_run<T, 64>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h);
+    case 1: return eig_run<T, 16>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
+    case 2: return eig_run<T, 32>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
+    case 3: return eig_run<T, 48>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
+    default: return eig_run<T, 64>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
   }
 }
 
@@ -923,4 +930,22 @@ extern "C" int fpca_eig_randomized(fpca_handle ctx, int dtype, int prec, const f
                             evals, static_cast<double *>(efuns), fve);
   return eig_impl<float>(ctx, grid, P, static_cast<const float *>(gamma), quad_w, k, oversample, power_iters, seed,
                          evals, static_cast<float *>(efuns), fve);
+}
+
+extern "C" int fpca_eig_covop(fpca_covop op, const double *quad_w, int k, int oversample, int power_iters,
+                              uint64_t seed, double *evals, double *efuns, double *fve) {
+  if (!op) return set_error(FPCA_ERR_INVALID_ARG, "null operator");
+  fpca_context *ctx = op->ctx;
+  if (int rc = check_handle(ctx)) return rc;
+  if (!evals || !efuns) return set_error(FPCA_ERR_INVALID_ARG, "evals and efuns are required");
+  if (k < 1 || oversample < 0 || power_iters < 0)
+    return set_error(FPCA_ERR_INVALID_ARG, "need k >= 1, oversample >= 0, power_iters >= 0");
+  if (k + oversample > 64 || k + oversample > op->P)
+    return set_error(FPCA_ERR_INVALID_ARG, "k + oversample = %d must be <= min(64, P)", k + oversample);
+  if (int rc = set_device(ctx)) return rc;
+  fpca_grid g{};
+  g.d = op->d;
+  for (int q = 0; q < 3; ++q) g.M[q] = q < op->d ? op->M[q] : 1;
+  g.mask = nullptr;
+  return eig_impl<double>(ctx, &g, op->P, nullptr, quad_w, k, oversample, power_iters, seed, evals, efuns, fve, op);
 }
