@@ -163,6 +163,94 @@ def cv_d3_timing(h, torch, F):
             "node_solves_per_s": sc.size * P * P / t_cv}
 
 
+def f2_timing(h, torch, F):
+    """Simulation II's shape (d=3, 64^3 grid, n=100 complete curves, h=0.1):
+    the smoothed covariance on 64^6 = 6.9e10 nodes (275 GB in FP32) is never
+    stored; the randomized eigendecomposition takes its products through the
+    covariance operator. The band part is recomputed in every product
+    (FPCA_COVOP_RECOMPUTE) and, as the alternative, kept as band blocks."""
+    from fpca_synth import make_sim2, sim2_eigfun, grid_points
+    log("covariance operator, d=3 64^3 (Simulation II shape)")
+    M, hb, k, over, q = 64, 0.1, 4, 12, 2
+    ds = make_sim2(M=M)
+    P = M ** 3
+    dev = "cuda:0"
+    g = F.Grid((M, M, M))
+    Y = torch.from_numpy(ds.y).to(dev)
+    c = torch.empty(P, dtype=torch.float64, device=dev)
+    s = torch.empty_like(c)
+    mu = torch.empty_like(c)
+    F.fpca_bin(h, g, F.FPCA_BIN_MEAN, F.FPCA_COMMON_GRID, F.FPCA_F64, F.FPCA_PREC_F64, ds.n, None, None, Y, None, 0,
+               c, s)
+    F.fpca_smooth_mean(h, g, F.FPCA_F64, c, s, F.FPCA_K_EPANECHNIKOV, hb, mu)
+    h.sync()
+    R = int(np.floor(hb * (M - 1)))
+    band_1d = sum(min(x + 2 * R, M - 1) - max(x - 2 * R, 0) + 1 for x in range(M))
+    band_pairs = band_1d ** 3
+    r = k + over
+    X = torch.randn(P, r, dtype=torch.float64, device=dev)
+    out = torch.empty(P, r, dtype=torch.float64, device=dev)
+    res = {"workload": "d=3 complete curves on 64^3, n=100, h=0.1 (13 taps per coordinate), k=4, r=16, q=2",
+           "cov_nodes": P * P, "band_pairs": band_pairs}
+
+    def timed(fn, reps=1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    pts = grid_points((M, M, M))
+    w = 1.0 / (M - 1) ** 3
+
+    def quality(ev, ef):
+        phi = ef.cpu().numpy()
+        ise = []
+        for l in range(1, 5):
+            tru = sim2_eigfun(l, pts)
+            tru = tru / np.sqrt(w * (tru ** 2).sum())
+            e = phi[l - 1]
+            sg = np.sign((e * tru).sum())
+            ise.append(float(w * ((sg * e - tru) ** 2).sum()))
+        return {"evals": [float(v) for v in ev], "ise_phi": ise}
+
+    op = F.CovOp(h, g, Y, mu, hb, F.FPCA_COVOP_RECOMPUTE)
+    try:
+        op.apply(X, out)
+        t_apply = timed(lambda: op.apply(X, out), 2)
+        ef = torch.empty(k, P, dtype=torch.float64, device=dev)
+        evh = {}
+        t_eig = timed(lambda: evh.update(v=op.eig(None, k, over, q, 7, ef)))
+        res["recompute"] = {"apply_ms": t_apply, "eig_ms": t_eig, **quality(evh["v"][0], ef)}
+    finally:
+        op.close()
+    flops = band_pairs * 2.0 * 7 * ds.n
+    res["roofline"] = {"bound": "fp64", "kernel": "k_band<3> (one product, r=16)",
+                       "alg_flops_per_band_pair": 2 * 7 * ds.n, "achieved": flops / (t_apply * 1e-3) / 1e12,
+                       "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (t_apply * 1e-3) / 1e12 / 78.6}
+    free, _ = torch.cuda.mem_get_info()
+    if free > (64 << 30):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = F.CovOp(h, g, Y, mu, hb, F.FPCA_COVOP_STORE_BAND)
+        torch.cuda.synchronize()
+        t_create = (time.perf_counter() - t0) * 1e3
+        try:
+            op.apply(X, out)
+            t_apply2 = timed(lambda: op.apply(X, out), 3)
+            ef = torch.empty(k, P, dtype=torch.float64, device=dev)
+            evh = {}
+            t_eig2 = timed(lambda: evh.update(v=op.eig(None, k, over, q, 7, ef)))
+            res["stored_band"] = {"create_ms": t_create, "apply_ms": t_apply2, "eig_ms": t_eig2,
+                                  **quality(evh["v"][0], ef)}
+        finally:
+            op.close()
+    res["lambda_true"] = [4.0 ** (3 - l) / 512 for l in range(1, 5)]
+    return res
+
+
 def f1_timing(h, torch, F, dd, ds, b):
     """Noise variance (eq. 2.6), PACE scores (eq. 2.7) and the reconstruction on
     the grid for the benchmark workload, from one step's smoothed mean,
@@ -224,6 +312,7 @@ def main():
     ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
     ap.add_argument("--no-hselect", action="store_true", help="skip the surrogate-versus-CV timing")
     ap.add_argument("--no-f1", action="store_true", help="skip the noise-variance, PACE and reconstruction timing")
+    ap.add_argument("--no-f2", action="store_true", help="skip the covariance-operator (64^3) timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
@@ -384,6 +473,7 @@ def main():
     out["hselect"] = None if args.no_hselect else hselect_timing(h, torch)
     if not args.no_cv_d3:
         out["cv_d3"] = cv_d3_timing(h, torch, F)
+    out["f2"] = None if args.no_f2 else f2_timing(h, torch, F)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         G_host = bufs.G.cpu().numpy().astype(np.float64)

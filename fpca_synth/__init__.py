@@ -14,6 +14,8 @@ from .generators import (  # noqa: F401
     make_c3,
     make_c4,
     make_surrogate_dataset,
+    make_sim2,
+    sim2_eigfun,
     irregular_kl,
     fourier_1d,
     grid_nodes,

@@ -248,5 +248,34 @@ def make_surrogate_dataset(index: int, split: str = "train", M: int = 32,
     return ds
 
 
+def sim2_eigfun(l: int, pts: np.ndarray) -> np.ndarray:
+    """Simulation II's l-th component as printed: prod_i sin(2 l pi t_i) / 2
+    (not unit norm: its squared L2 norm on [0,1]^3 is (1/8)^3)."""
+    return np.prod(np.sin(2 * l * np.pi * pts) / 2.0, axis=1)
+
+
+def make_sim2(seed: int = 1006, n: int = 100, M: int = 64, noise_sd: float = 0.25,
+              dtype=np.float64) -> Dataset:
+    """Simulation II's model on a complete M^3 grid: mu(t) = exp(|t - 1/2|^2),
+    Y_i = mu + sum_{l=1..4} A_il phi_l + eps with A_il ~ N(0, 4^(3-l)),
+    phi_l as printed (see sim2_eigfun) and eps ~ N(0, 1/16); n = 100 curves.
+    The covariance's eigenpairs are lambda_l = 4^(3-l) ||phi_l||^2 with
+    eigenfunctions phi_l / ||phi_l||. h = 0.1 (6 grid steps at M = 64)."""
+    rng = np.random.default_rng(seed)
+    pts = grid_points((M, M, M))
+    P = pts.shape[0]
+    mu = np.exp(((pts - 0.5) ** 2).sum(1))
+    A = rng.standard_normal((n, 4)) * np.sqrt(4.0 ** (3 - np.arange(1, 5)))
+    Phi = np.stack([sim2_eigfun(l, pts) for l in range(1, 5)])
+    y = np.empty((n, P), dtype=dtype)
+    for i in range(n):
+        y[i] = mu + A[i] @ Phi + noise_sd * rng.standard_normal(P)
+    ds = Dataset("sim2", 3, "common", n, None, None, y, (M, M, M), (M, M, M), 0.1, 0.1,
+                 "f64" if dtype == np.float64 else "f32", k=4, oversample=12, power_iters=2)
+    ds.extra["mu"] = mu
+    ds.extra["scores"] = A
+    return ds
+
+
 def make_config(k: int, **kw) -> Dataset:
     return {1: make_c1, 2: make_c2, 3: make_c3, 4: make_c4}[k](**kw)

@@ -175,6 +175,24 @@ int fpca_smooth_mean(fpca_handle handle, const fpca_grid *grid, int dtype, const
 int fpca_set_conv(fpca_handle handle, int mode);
 
 /*
+ * fpca_set_engine -- which engine smooths the covariance for general pair
+ * weights (fpca_smooth_cov with C given, fpca_cv_batched; fpca_cv_loo always
+ * runs the queue kernel):
+ * FPCA_ENGINE_QUEUE is the persistent task-queue kernel (one launch, FP64
+ * moments kept on chip between passes; grids of P <= 4096 with M <= 64 for
+ * d = 1, 32 x 64 for d = 2, 16^3 for d = 3); FPCA_ENGINE_PASSES the 1-D pass
+ * engine (FP64 moment arrays in device memory between passes, any grid);
+ * FPCA_ENGINE_AUTO (default) takes the queue kernel when the pass engine's
+ * arrays would not fit in the 256 MB Infinity Cache, and batched CV also
+ * times the job-by-job pass engine against the queue kernel's tile shapes.
+ * Both engines compute the same sums in FP64 (results agree to rounding).
+ */
+#define FPCA_ENGINE_AUTO 0
+#define FPCA_ENGINE_QUEUE 1
+#define FPCA_ENGINE_PASSES 2
+int fpca_set_engine(fpca_handle handle, int engine);
+
+/*
  * fpca_smooth_cov -- the covariance (eq. 2.4): the same smoother on the
  * 2d-dimensional grid of (s, t) pairs, applied to the pair weights C and raw
  * products G from fpca_bin kind COV (slab 0), giving b0(s,t), then

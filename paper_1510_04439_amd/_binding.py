@@ -29,6 +29,7 @@ FPCA_PREC_F64, FPCA_PREC_F32, FPCA_PREC_BF16X3 = 0, 1, 2
 FPCA_K_EPANECHNIKOV = 0
 FPCA_CONV_DIRECT, FPCA_CONV_FFT, FPCA_CONV_AUTO = 0, 1, 2
 FPCA_COVOP_RECOMPUTE, FPCA_COVOP_STORE_BAND = 0, 1
+FPCA_ENGINE_AUTO, FPCA_ENGINE_QUEUE, FPCA_ENGINE_PASSES = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
@@ -37,6 +38,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
     "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
     "fpca_set_conv", "fpca_covop_create", "fpca_covop_apply", "fpca_covop_destroy", "fpca_eig_covop",
+    "fpca_set_engine",
 ]
 
 
@@ -71,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     L.fpca_set_stream.argtypes = [vp, vp]
     L.fpca_sync.argtypes = [vp]
     L.fpca_set_conv.argtypes = [vp, i32]
+    L.fpca_set_engine.argtypes = [vp, i32]
     L.fpca_covop_create.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, ctypes.POINTER(ctypes.c_double), i32,
                                     ctypes.POINTER(vp)]
     L.fpca_covop_apply.argtypes = [vp, i32, vp, vp]
@@ -351,6 +354,11 @@ def fpca_bw_search(h: Handle, grid: Grid, dtype: int, C, G, Q, h_lo, h_hi, h_ini
                                          int(max_evals), hout.ctypes.data_as(P), cv.ctypes.data_as(P),
                                          ctypes.byref(n), trace.ctypes.data_as(P)))
     return hout, float(cv[0]), int(n.value), trace[:min(n.value, max_evals)]
+
+
+def fpca_set_engine(h: Handle, engine: int):
+    """Covariance smoother engine: FPCA_ENGINE_AUTO, FPCA_ENGINE_QUEUE or FPCA_ENGINE_PASSES."""
+    _check(load_library().fpca_set_engine(h.ptr, int(engine)))
 
 
 def fpca_set_conv(h: Handle, mode: int):

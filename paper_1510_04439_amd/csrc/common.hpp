@@ -47,6 +47,8 @@ struct fpca_context {
   // has timed, per pass shape.
   int conv_mode = FPCA_CONV_DIRECT;
   std::vector<std::pair<std::vector<int64_t>, int>> conv_cache;
+  // Covariance smoother engine for general pair weights (FPCA_ENGINE_*).
+  int engine = FPCA_ENGINE_AUTO;
   // Tile shapes chosen by the autotuner, per batched-CV shape key.
   std::vector<std::pair<std::vector<double>, std::pair<int, int>>> tune_cache;
 };
@@ -76,6 +78,10 @@ int ws3_reserve(fpca_context *ctx, size_t bytes);
 // previous upload from it first.
 int tables_stage(fpca_context *ctx, size_t bytes, char **out);
 
+// Whether the persistent task-queue engine runs a covariance smoother on this
+// grid under the handle's engine setting (AUTO: when the pass engine's FP64
+// moment arrays would not fit in the 256 MB Infinity Cache).
+bool use_queue_engine(const fpca_context *ctx, const fpca_grid *grid);
 // Covariance smoother behind fpca_smooth_cov (arguments already validated).
 int smooth_cov_internal(fpca_context *ctx, const fpca_grid *grid, int dtype, const void *C, double c_uniform,
                         const void *G, const void *mu, const double *bw, void *gamma, int8_t *status);

@@ -12,11 +12,13 @@
 // Every (dataset, bandwidth, fold) job of a call runs in one persistent launch
 // of the task-queue smoother (smooth_tiled.hip). Its tile shape (t-columns per
 // task) and the number of persistent workgroups per compute unit are chosen
-// per shape by timing the candidates that fit in LDS on the first call; the
+// per shape by timing the candidates that fit in LDS on the first call (with
+// the job-by-job general pass engine as one more candidate); the
 // second call with the same shape captures the launch into a HIP graph, later
 // calls replay it (the job table, which holds the callers' pointers, is
 // uploaded before each launch, outside the graph). Grids the queue smoother
 // does not take run job by job through the general pass engine.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -132,7 +134,7 @@ template <typename T>
 int cv_impl(fpca_context *ctx, int dtype, int n_data, const fpca_cv_data *data, int n_folds, int n_h,
             const double *bw, double *scores_h) {
   const int d = data[0].grid.d;
-  bool all_tiled = true;
+  bool all_tiled = ctx->engine != FPCA_ENGINE_PASSES;
   for (int a = 0; a < n_data; ++a) all_tiled = all_tiled && tiled_supported(&data[a].grid);
   if (!all_tiled) {
     for (int a = 0; a < n_data; ++a)
@@ -182,11 +184,43 @@ int cv_impl(fpca_context *ctx, int dtype, int n_data, const fpca_cv_data *data, 
       cfg.wg_per_cu = e.second.second;
       tuned = true;
     }
+  // qb = 0 stands for the job-by-job general pass engine (small grids whose
+  // FP64 intermediates stay in the caches can run faster that way)
+  auto run_general = [&]() -> int {
+    for (int a = 0; a < n_data; ++a)
+      if (int rc = cv_general<T>(ctx, data[a], dtype, n_folds, n_h, bw, scores_h + int64_t(a) * n_h * n_folds))
+        return rc;
+    return FPCA_OK;
+  };
   if (!tuned) {
     hipEvent_t e0, e1;
     FPCA_HIP(hipEventCreate(&e0));
     FPCA_HIP(hipEventCreate(&e1));
     float best = 1e30f;
+    // the job-by-job engine is a candidate when one job's FP64 moment arrays
+    // (1 + D + D(D+1)/2 + 1 + D of them) fit in the 256 MB Infinity Cache;
+    // its first run sizes its scratch, the second is timed
+    size_t foot = 0;
+    for (int a = 0; a < n_data; ++a) {
+      const int64_t PP = grid_P(data[a].grid) * grid_P(data[a].grid);
+      const int D = 2 * d;
+      foot = std::max(foot, size_t(PP) * 8 * size_t(2 + 2 * D + D * (D + 1) / 2));
+    }
+    if (ctx->engine == FPCA_ENGINE_AUTO && foot <= (size_t(256) << 20)) {
+      int rc = run_general();
+      if (rc == FPCA_OK) rc = hipEventRecord(e0, ctx->stream) == hipSuccess ? FPCA_OK : FPCA_ERR_DEVICE;
+      if (rc == FPCA_OK) rc = run_general();
+      if (rc == FPCA_OK) rc = hipEventRecord(e1, ctx->stream) == hipSuccess ? FPCA_OK : FPCA_ERR_DEVICE;
+      if (rc == FPCA_OK) rc = hipEventSynchronize(e1) == hipSuccess ? FPCA_OK : FPCA_ERR_DEVICE;
+      if (rc != FPCA_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc == FPCA_ERR_DEVICE ? set_error(rc, "batched CV: timing the job-by-job engine failed") : rc;
+      }
+      FPCA_HIP(hipEventElapsedTime(&best, e0, e1));
+      cfg.qb = 0;
+      cfg.wg_per_cu = 0;
+    }
     for (int qb : {8, 16}) {
       const size_t lds = tiled_lds(jobs, qb);
       if (!lds) continue;
@@ -219,6 +253,7 @@ int cv_impl(fpca_context *ctx, int dtype, int n_data, const fpca_cv_data *data, 
     if (best >= 1e30f) return set_error(FPCA_ERR_UNSUPPORTED, "batched CV: no tile shape fits in LDS");
     ctx->tune_cache.push_back({shape, {cfg.qb, cfg.wg_per_cu}});
   }
+  if (cfg.qb == 0) return run_general();
   TiledLaunch L;
   if (int rc = tiled_plan<T>(ctx, jobs, true, cfg, &L)) return rc;
   // graph key: the shape, the chosen configuration and the scratch layout

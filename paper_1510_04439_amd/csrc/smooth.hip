@@ -576,7 +576,7 @@ int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double
     if (!C && smooth_cov_fused_d2_supported(grid, bw))
       return smooth_cov_fused_d2(ctx, grid, c_uniform, G, bw, mu, gamma, status);
   }
-  if (tiled_supported(grid)) {
+  if (use_queue_engine(ctx, grid)) {
     // the persistent-queue engine: FP64 moments kept on chip between passes
     std::vector<TiledJob> jobs(1);
     TiledJob &j = jobs[0];
@@ -625,6 +625,17 @@ int smooth_cov_impl(fpca_context *ctx, const fpca_grid *grid, const T *C, double
 }
 
 }  // namespace
+
+bool use_queue_engine(const fpca_context *ctx, const fpca_grid *grid) {
+  if (!tiled_supported(grid) || ctx->engine == FPCA_ENGINE_PASSES) return false;
+  if (ctx->engine == FPCA_ENGINE_QUEUE) return true;
+  int64_t P = 1;
+  for (int k = 0; k < grid->d; ++k) P *= grid->M[k];
+  const int D = 2 * grid->d;
+  const double foot = double(P) * double(P) * 8.0 * double(2 + 2 * D + D * (D + 1) / 2);
+  return foot > double(256 << 20);
+}
+
 }  // namespace fpca
 
 using namespace fpca;
@@ -678,5 +689,13 @@ extern "C" int fpca_set_conv(fpca_handle ctx, int mode) {
   if (mode != FPCA_CONV_DIRECT && mode != FPCA_CONV_FFT && mode != FPCA_CONV_AUTO)
     return set_error(FPCA_ERR_INVALID_ARG, "bad convolution mode %d", mode);
   ctx->conv_mode = mode;
+  return FPCA_OK;
+}
+
+extern "C" int fpca_set_engine(fpca_handle ctx, int engine) {
+  if (int rc = check_handle(ctx)) return rc;
+  if (engine != FPCA_ENGINE_AUTO && engine != FPCA_ENGINE_QUEUE && engine != FPCA_ENGINE_PASSES)
+    return set_error(FPCA_ERR_INVALID_ARG, "bad engine %d", engine);
+  ctx->engine = engine;
   return FPCA_OK;
 }

@@ -1,4 +1,6 @@
 """Helpers shared by the test modules (no method arithmetic here)."""
+import contextlib
+
 import numpy as np
 
 
@@ -35,3 +37,13 @@ def rand_irregular(rng, d, n, Nlo, Nhi, dtype=np.float32):
     t = rng.random((int(off[-1]), d)).astype(dtype)
     y = rng.standard_normal(int(off[-1])).astype(dtype)
     return off, t, y
+
+
+@contextlib.contextmanager
+def engine(F, h, e):
+    """Runs the block with the handle's covariance engine set to e (then AUTO)."""
+    F.fpca_set_engine(h, e)
+    try:
+        yield
+    finally:
+        F.fpca_set_engine(h, F.FPCA_ENGINE_AUTO)

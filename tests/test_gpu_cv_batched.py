@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from fpca_synth import disk_time_mask, fold_assignment
-from tests._util import rand_irregular
+from tests._util import rand_irregular, engine
 
 pytestmark = pytest.mark.gpu
 
@@ -70,8 +70,14 @@ def _ref_scores(M, hs, nf, C, G, Q, mask=None):
     ("f64", [(4, 5, 4), (3, 4, 5)], [24, 11], [0.3, 0.55], 4),
     ("f32", [(40,), (23,)], [20, 35], [0.05, 0.12, 0.3], 5),
 ])
-def test_cv_batched_uneven_datasets(torch, F, h, dt, grids, ns, hs, nf):
-    _say(f"cv uneven datasets {dt} grids={grids} n={ns} h={hs} folds={nf}")
+@pytest.mark.parametrize("eng", ["queue", "passes"])
+def test_cv_batched_uneven_datasets(torch, F, h, dt, grids, ns, hs, nf, eng):
+    with engine(F, h, F.FPCA_ENGINE_QUEUE if eng == "queue" else F.FPCA_ENGINE_PASSES):
+        _cv_uneven(torch, F, h, dt, grids, ns, hs, nf, eng)
+
+
+def _cv_uneven(torch, F, h, dt, grids, ns, hs, nf, eng):
+    _say(f"cv uneven datasets {dt} grids={grids} n={ns} h={hs} folds={nf} engine={eng}")
     rng = np.random.default_rng(900 + len(grids[0]))
     npdt = np.float64 if dt == "f64" else np.float32
     data, host = [], []
@@ -104,7 +110,8 @@ def test_cv_batched_masked_d3_many_jobs_and_select(torch, F, h):
     C, G, Q = _dataset(rng, M, 30, nf, np.float32, seed=4)
     D = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
     _say(f"cv masked d=3 M={M} jobs={len(hs) * nf}")
-    scores = F.fpca_cv_batched(h, F.FPCA_F32, [(F.Grid(M, D(mask)), D(C), D(G), D(Q))], nf, hs)[0]
+    with engine(F, h, F.FPCA_ENGINE_QUEUE):  # slot reuse across jobs is the queue kernel's
+        scores = F.fpca_cv_batched(h, F.FPCA_F32, [(F.Grid(M, D(mask)), D(C), D(G), D(Q))], nf, hs)[0]
     ref = _ref_scores(M, hs, nf, C, G, Q, mask)
     np.testing.assert_allclose(scores, ref, rtol=1e-5)
     h_gpu = F.fpca_cv_select(hs, scores.sum(1))[0]

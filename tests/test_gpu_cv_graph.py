@@ -47,9 +47,11 @@ def test_cv_graph_replays_match_eager(torch, F, M, hs):
     refs = {}
     for name, X in (("A", A), ("B", Bs)):
         he = F.Handle(0)
+        F.fpca_set_engine(he, F.FPCA_ENGINE_QUEUE)  # graphs are the queue kernel's
         refs[name] = F.fpca_cv_batched(he, F.FPCA_F32, [(g, *X)], nf, hs)[0]
         he.close()
     h = F.Handle(0)
+    F.fpca_set_engine(h, F.FPCA_ENGINE_QUEUE)
     seq = ["A", "B", "A", "B", "B", "A"]  # eager, capture, replays
     for i, name in enumerate(seq):
         X = A if name == "A" else Bs

@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 from fpca_synth import disk_time_mask, fold_assignment, make_c3, make_c4
-from tests._util import normwise_rel, rand_irregular, status_agreement
+from tests._util import engine, normwise_rel, rand_irregular, status_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +78,13 @@ def _check_masked(gam_h, st_h, ref, rst, mask, tol):
 
 
 @pytest.mark.parametrize("M,hb", [((12, 12), 0.25), ((6, 6, 6), 0.45), ((7, 5, 6), 0.5)])
-def test_smooth_cov_masked_general(torch, F, h, M, hb):
+@pytest.mark.parametrize("eng", ["queue", "passes"])
+def test_smooth_cov_masked_general(torch, F, h, M, hb, eng):
+    with engine(F, h, F.FPCA_ENGINE_QUEUE if eng == "queue" else F.FPCA_ENGINE_PASSES):
+        _masked_general(torch, F, h, M, hb)
+
+
+def _masked_general(torch, F, h, M, hb):
     """Pair weights from irregular curves (the general FP64-moment path) on a
     masked grid: disk in the first two coordinates (times [0,1] for d = 3)."""
     _say(f"masked smooth_cov general M={M} h={hb}")
@@ -126,7 +132,13 @@ def test_smooth_cov_masked_common_grid(torch, F, h, M, hb):
 
 
 @pytest.mark.parametrize("M,nf,hs", [((6, 6, 6), 3, [0.3, 0.5]), ((10, 10), 4, [0.15, 0.3])])
-def test_cv_batched_masked(torch, F, h, M, nf, hs):
+@pytest.mark.parametrize("eng", ["queue", "passes"])
+def test_cv_batched_masked(torch, F, h, M, nf, hs, eng):
+    with engine(F, h, F.FPCA_ENGINE_QUEUE if eng == "queue" else F.FPCA_ENGINE_PASSES):
+        _cv_masked(torch, F, h, M, nf, hs)
+
+
+def _cv_masked(torch, F, h, M, nf, hs):
     """Masked CV: the held-out pairs are scored against the training smooth,
     which is 0 at nodes outside Omega (as the covariance there)."""
     _say(f"masked cv M={M} folds={nf} h={hs}")

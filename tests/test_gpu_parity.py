@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from fpca_synth import grid_points, make_c1, make_c2, fourier_1d, disk_time_mask, fold_assignment
-from tests._util import normwise_rel, rand_irregular, status_agreement
+from tests._util import engine, normwise_rel, rand_irregular, status_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -320,11 +320,21 @@ def _cov_inputs(rng, M, d):
     return C.astype(np.float32), G.astype(np.float32)
 
 
-@pytest.mark.parametrize("M,hb,dt,sample", [((51,), 0.1, "f64", 0), ((12, 12), 0.2, "f32", 0),
-                                            ((6, 6, 6), 0.45, "f32", 0), ((32, 32), 0.08, "f32", 3000),
-                                            ((11, 14), 0.25, "f32", 0), ((24, 24), 0.27, "f32", 1500),
-                                            ((7, 9), 0.6, "f32", 0), ((64, 64), 0.1, "f32", 800)])
-def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample):
+_COV_CASES = [((51,), 0.1, "f64", 0), ((12, 12), 0.2, "f32", 0), ((6, 6, 6), 0.45, "f32", 0),
+              ((32, 32), 0.08, "f32", 3000), ((11, 14), 0.25, "f32", 0), ((24, 24), 0.27, "f32", 1500),
+              ((7, 9), 0.6, "f32", 0), ((64, 64), 0.1, "f32", 800)]
+
+
+# both engines on the small grids; the large ones (sampled nodes) run the
+# queue kernel, as AUTO does for them
+@pytest.mark.parametrize("M,hb,dt,sample,eng", [c + ("queue",) for c in _COV_CASES] +
+                         [c + ("passes",) for c in _COV_CASES if c[3] == 0])
+def test_smooth_cov_parity(torch, F, h, M, hb, dt, sample, eng):
+    with engine(F, h, F.FPCA_ENGINE_QUEUE if eng == "queue" else F.FPCA_ENGINE_PASSES):
+        _smooth_cov_parity(torch, F, h, M, hb, dt, sample)
+
+
+def _smooth_cov_parity(torch, F, h, M, hb, dt, sample):
     _say(f"smooth_cov M={M} h={hb} {dt} sample={sample}")
     rng = np.random.default_rng(300 + sum(M))
     d = len(M)
