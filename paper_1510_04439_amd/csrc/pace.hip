@@ -61,63 +61,263 @@ __device__ inline void chol_solve(const double (*L)[PACE_KMAX + 1], double *x, i
   }
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Four consecutive values as FP64 from one 16-byte (float) or two 16-byte
+// (double) loads; the address is 16-byte aligned.
+__device__ inline void load4(const float *p, double *o) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ inline void load4(const double *p, double *o) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+  o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+}
+constexpr int CG_THREADS = 1024;  // 16 wavefronts
+constexpr int MB = 8;             // MFMA steps (4 nodes each) whose operands are loaded together
+
 // Common grid: the factor of Phi^T Phi + sigma^2 Lambda^{-1} over all P nodes,
-// shared by every curve observed at all of them. One workgroup: the basis in
-// chunks of 64 nodes through LDS, thread e accumulates upper-triangle entry e
-// in node order; thread 0 factors. ok[0] = 1 on success.
-template <typename T>
-__global__ __launch_bounds__(PACE_THREADS) void k_pace_cg_prep(int64_t P, const T *__restrict__ efuns, int k,
-                                                               PaceDiag dg, double *__restrict__ Lout,
-                                                               int *__restrict__ ok) {
-  __shared__ double ph[PACE_CH][PACE_KMAX + 1];
+// shared by every curve observed at all of them. One workgroup: wavefront w
+// takes a contiguous sixteenth of the nodes and accumulates the 16 x 16 tiles
+// (tr, tc) of Phi^T Phi with FP64 MFMA (16 x 16 x 4: lane l carries
+// Phi[16 tr + l % 16][node + l / 16] as the A operand and the same for tc as
+// the B operand), the operands of MB steps loaded before they are used; the
+// sixteen partial tiles are summed in a fixed order (waves 4g + w, g = 0..3,
+// into slot w, then the four slots); its inverse (below) goes to Lout.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int64_t P, const T *__restrict__ efuns, int k,
+                                                             PaceDiag dg, double *__restrict__ Lout,
+                                                             int *__restrict__ ok) {
+  __shared__ double part[4][2][2][256];
   __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
-  __shared__ unsigned char tri_r[PACE_TRI], tri_c[PACE_TRI];
-  const int tid = threadIdx.x;
-  const int nmat = k * (k + 1) / 2;
-  if (tid == 0)
-    for (int r = 0, e = 0; r < k; ++r)
-      for (int c = r; c < k; ++c, ++e) {
-        tri_r[e] = (unsigned char)r;
-        tri_c[e] = (unsigned char)c;
+  __shared__ double Mb[PACE_KMAX][2 * PACE_KMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = k > 16 ? 2 : 1;
+  const int row = lane & 15, kk = lane >> 4;
+  constexpr int NW = CG_THREADS / 64;
+  const int64_t per = ((P + NW * 4 * MB - 1) / (NW * 4 * MB)) * 4 * MB;  // nodes per wavefront
+  const int64_t n0 = wave * per, n1 = min(P, n0 + per);
+  v4d d00 = {0, 0, 0, 0}, d01 = d00, d11 = d00;
+  const bool r0 = row < k, r1 = 16 + row < k;
+  const T *f0p = efuns + int64_t(r0 ? row : 0) * P;
+  const T *f1p = efuns + int64_t(r1 ? 16 + row : 0) * P;
+  for (int64_t q = n0; q < n1; q += 4 * MB) {
+    double f0[MB], f1[MB];
+    if (VEC && q + 4 * MB <= n1) {
+      // step 4b + j takes node q + 16 b + 4 kk + j: each lane's four nodes of
+      // a 16-node block in one vector load
+#pragma unroll
+      for (int bl = 0; bl < MB / 4; ++bl) {
+        const int64_t p = q + 16 * bl + 4 * kk;
+        load4(f0p + p, f0 + 4 * bl);
+        load4(f1p + p, f1 + 4 * bl);
       }
-  double acc[PACE_ACC];
 #pragma unroll
-  for (int q = 0; q < PACE_ACC; ++q) acc[q] = 0.0;
-  for (int64_t c0 = 0; c0 < P; c0 += PACE_CH) {
-    const int m = int(min(int64_t(PACE_CH), P - c0));
-    __syncthreads();
-    if (tid < m)
-      for (int l = 0; l < k; ++l) ph[tid][l] = double(efuns[int64_t(l) * P + c0 + tid]);
-    __syncthreads();
+      for (int s = 0; s < MB; ++s) {
+        f0[s] = r0 ? f0[s] : 0.0;
+        f1[s] = r1 ? f1[s] : 0.0;
+      }
+    } else {
+      // every load is issued (addresses clamped into the range), then masked
 #pragma unroll
-    for (int q = 0; q < PACE_ACC; ++q) {
-      const int e = tid + PACE_THREADS * q;
-      if (e < nmat) {
-        const int r = tri_r[e], c = tri_c[e];
-        double sum = 0.0;
-        for (int o = 0; o < m; ++o) sum += ph[o][r] * ph[o][c];
-        acc[q] += sum;
+      for (int s = 0; s < MB; ++s) {
+        const int64_t p = q + 16 * (s >> 2) + 4 * kk + (s & 3);
+        const int64_t pc = min(p, n1 - 1);
+        const double v0 = double(f0p[pc]), v1 = double(f1p[pc]);
+        const bool in = p < n1;
+        f0[s] = (in && r0) ? v0 : 0.0;
+        f1[s] = (in && r1) ? v1 : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+      d00 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[s], f0[s], d00, 0, 0, 0);
+      if (nt > 1) {  // tile (1, 0) is the transpose of (0, 1)
+        d01 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[s], f1[s], d01, 0, 0, 0);
+        d11 = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[s], f1[s], d11, 0, 0, 0);
       }
     }
   }
-  __syncthreads();
+  // D[i][j] of a tile sits in lane j + 16 (i % 4), element i / 4; waves
+  // 4g .. 4g + 3 add into the four slots in turn (g = 0 writes)
+  for (int g = 0; g < NW / 4; ++g) {
+    if ((wave >> 2) == g) {
+      const int w = wave & 3;
 #pragma unroll
-  for (int q = 0; q < PACE_ACC; ++q) {
-    const int e = tid + PACE_THREADS * q;
-    if (e < nmat) {
-      const int r = tri_r[e], c = tri_c[e];
-      const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
-      const double v = (kr && kc) ? acc[q] + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
-      A[r][c] = v;
-      A[c][r] = v;
+      for (int v = 0; v < 4; ++v) {
+        const int e = (kk + 4 * v) * 16 + row;
+        part[w][0][0][e] = (g ? part[w][0][0][e] : 0.0) + d00[v];
+        part[w][0][1][e] = (g ? part[w][0][1][e] : 0.0) + d01[v];
+        part[w][1][1][e] = (g ? part[w][1][1][e] : 0.0) + d11[v];
+      }
     }
+    __syncthreads();
+  }
+  for (int e = tid; e < k * k; e += CG_THREADS) {
+    const int r = e / k, c = e % k;
+    // the upper tiles only: entry (r, c) of tile (1, 0) is (c, r) of tile (0, 1)
+    const int rr = (r >> 4) > (c >> 4) ? c : r, cc = (r >> 4) > (c >> 4) ? r : c;
+    const int tr = rr >> 4, tc = cc >> 4;
+    const int ei = (rr & 15) * 16 + (cc & 15);
+    double sum = 0.0;
+    for (int w = 0; w < 4; ++w) sum += part[w][tr][tc][ei];
+    const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
+    A[r][c] = (kr && kc) ? sum + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (tid == 0) {
-    const bool good = chol_inplace(A, k);
-    for (int r = 0; r < k; ++r)
-      for (int c = 0; c < k; ++c) Lout[r * k + c] = A[r][c];
-    ok[0] = good ? 1 : 0;
+  // A^{-1} by Gauss-Jordan elimination on [A | I] (k x 2k), two LDS buffers
+  // so that each step reads the previous one: one barrier per step. A is
+  // symmetric positive definite when every kept component has lambda > 0;
+  // the pivots are those of its LDL^T factorization, so a pivot <= 0 means it
+  // is not: ok[0] = 0 (every curve then takes its own factorization).
+  double *M0 = &part[0][0][0][0], *M1 = &Mb[0][0];  // [PACE_KMAX][2 PACE_KMAX]
+  constexpr int LDM = 2 * PACE_KMAX;
+  for (int e = tid; e < k * 2 * k; e += CG_THREADS) {
+    const int r = e / (2 * k), j = e % (2 * k);
+    M0[r * LDM + j] = j < k ? A[r][j] : (j - k == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  bool good = true;
+  for (int c = 0; c < k; ++c) {
+    const double *Mo = (c & 1) ? M1 : M0;
+    double *Mn = (c & 1) ? M0 : M1;
+    const double piv = Mo[c * LDM + c];
+    good = good && piv > 0.0;
+    const double inv = 1.0 / piv;
+    for (int e = tid; e < k * 2 * k; e += CG_THREADS) {
+      const int r = e / (2 * k), j = e % (2 * k);
+      const double pj = Mo[c * LDM + j] * inv;
+      Mn[r * LDM + j] = r == c ? pj : fma(-Mo[r * LDM + c], pj, Mo[r * LDM + j]);
+    }
+    __syncthreads();
+  }
+  const double *Mf = (k & 1) ? M1 : M0;
+  for (int e = tid; e < k * k; e += CG_THREADS) Lout[e] = Mf[(e / k) * LDM + k + e % k];
+  if (tid == 0) ok[0] = good ? 1 : 0;
+}
+
+// Common grid, curves observed at every node: the right-hand sides
+// Phi^T (Y_i - mu) of 16 curves per workgroup as one FP64 MFMA product
+// (rows = curves, columns = components, K = nodes). Each of the eight
+// wavefronts streams an eighth of the nodes straight from memory into the
+// operands (lane l: Y[curve l % 16][node + l / 16] minus mu, and the basis at
+// the same node for components l % 16 and 16 + l % 16), MB steps loaded
+// before they are used; the wavefronts' tiles are summed in a fixed order. A
+// curve with a missing value
+// gets a NaN first score: k_pace solves it on its own. The scores are the
+// shared inverse times the right-hand sides.
+constexpr int RH_CURVES = 16;
+
+constexpr int RH_THREADS = 512;  // 8 wavefronts
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(RH_THREADS) void k_pace_cg_rhs(int64_t n, int64_t P, const T *__restrict__ y,
+                                                      const T *__restrict__ mu, const T *__restrict__ efuns, int k,
+                                                      PaceDiag dg, const double *__restrict__ Lcg,
+                                                      const int *__restrict__ cg_ok, T *__restrict__ scores) {
+  __shared__ double red[4][2][256];
+  __shared__ double Ai[PACE_KMAX][PACE_KMAX + 1];
+  __shared__ double rhs[RH_CURVES][PACE_KMAX + 1];
+  constexpr int NW = RH_THREADS / 64;
+  __shared__ int miss[RH_CURVES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c0 = int64_t(blockIdx.x) * RH_CURVES;
+  if (cg_ok[0] != 1) return;  // no shared factor: k_pace does every curve
+  for (int e = tid; e < k * k; e += RH_THREADS) Ai[e / k][e % k] = Lcg[e];
+  if (tid < RH_CURVES) miss[tid] = 0;
+  __syncthreads();
+  const int nt = k > 16 ? 2 : 1;
+  const int row = lane & 15, kk = lane >> 4;
+  const int64_t c = c0 + row;
+  const bool cin = c < n;
+  const T *yr = y + (cin ? c : 0) * P;
+  const bool r0 = row < k, r1 = 16 + row < k;
+  const T *f0p = efuns + int64_t(r0 ? row : 0) * P;
+  const T *f1p = efuns + int64_t(r1 ? 16 + row : 0) * P;
+  const int64_t per = ((P + NW * 4 * MB - 1) / (NW * 4 * MB)) * 4 * MB;
+  const int64_t n0 = wave * per, n1 = min(P, n0 + per);
+  v4d d0 = {0, 0, 0, 0}, d1 = d0;
+  bool bad = false;
+  for (int64_t q = n0; q < n1; q += 4 * MB) {
+    double a[MB], b0[MB], b1[MB];
+    if (VEC && q + 4 * MB <= n1) {
+      // step 4b + j takes node q + 16 b + 4 kk + j: each lane's four nodes of
+      // a 16-node block in one vector load per array
+      double ml[MB];
+#pragma unroll
+      for (int bl = 0; bl < MB / 4; ++bl) {
+        const int64_t p = q + 16 * bl + 4 * kk;
+        load4(yr + p, a + 4 * bl);
+        load4(mu + p, ml + 4 * bl);
+        load4(f0p + p, b0 + 4 * bl);
+        load4(f1p + p, b1 + 4 * bl);
+      }
+#pragma unroll
+      for (int s = 0; s < MB; ++s) {
+        const double yv = cin ? a[s] : 0.0;
+        bad |= !isfinite(yv);
+        a[s] = cin ? yv - ml[s] : 0.0;
+        b0[s] = r0 ? b0[s] : 0.0;
+        b1[s] = r1 ? b1[s] : 0.0;
+      }
+    } else {
+      // every load is issued (addresses clamped into the range), then masked
+#pragma unroll
+      for (int s = 0; s < MB; ++s) {
+        const int64_t p = q + 16 * (s >> 2) + 4 * kk + (s & 3);
+        const int64_t pc = min(p, n1 - 1);
+        const double yl = double(yr[pc]), ml = double(mu[pc]), v0 = double(f0p[pc]), v1 = double(f1p[pc]);
+        const bool in = p < n1 && cin;
+        const double yv = in ? yl : 0.0;
+        bad |= !isfinite(yv);
+        a[s] = in ? yv - ml : 0.0;
+        b0[s] = (p < n1 && r0) ? v0 : 0.0;
+        b1[s] = (p < n1 && r1) ? v1 : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b0[s], d0, 0, 0, 0);
+      if (nt > 1) d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b1[s], d1, 0, 0, 0);
+    }
+  }
+  if (bad) miss[row] = 1;
+  // D[i][j] sits in lane j + 16 (i % 4), element i / 4 (i: curve, j:
+  // component); waves 4g .. 4g + 3 add into the four slots in turn
+  for (int g = 0; g < NW / 4; ++g) {
+    if ((wave >> 2) == g) {
+      const int w = wave & 3;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = (kk + 4 * v) * 16 + row;
+        red[w][0][e] = (g ? red[w][0][e] : 0.0) + d0[v];
+        red[w][1][e] = (g ? red[w][1][e] : 0.0) + d1[v];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < RH_CURVES * PACE_KMAX; e += RH_THREADS) {
+    const int ci = e / PACE_KMAX, l = e % PACE_KMAX;
+    if (l >= k) continue;
+    const int tc = l >> 4, ei = ci * 16 + (l & 15);
+    double sum = 0.0;
+    for (int w = 0; w < 4; ++w) sum += red[w][tc][ei];
+    rhs[ci][l] = dg.v[l] >= 0.0 ? sum : 0.0;
+  }
+  __syncthreads();
+  // scores = A^{-1} rhs, one thread per (curve, component)
+  if (tid < RH_CURVES * k) {
+    const int ci = tid / k, l = tid % k;
+    const int64_t cc = c0 + ci;
+    if (cc < n) {
+      double v = 0.0;
+      for (int m = 0; m < k; ++m) v = fma(Ai[l][m], rhs[ci][m], v);
+      if (miss[ci]) {
+        if (l == 0) scores[cc * k] = T(__builtin_nan(""));  // marker: k_pace solves this curve
+      } else {
+        scores[cc * k + l] = T(v);
+      }
+    }
   }
 }
 
@@ -136,8 +336,6 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
                                                        const double *__restrict__ Lcg, const int *__restrict__ cg_ok,
                                                        T *__restrict__ scores) {
   __shared__ double ph[PACE_CH][PACE_KMAX + 1];
-  __shared__ double Lc[PACE_KMAX][PACE_KMAX + 1];
-  __shared__ double red[PACE_THREADS / 64][PACE_KMAX];
   __shared__ double yc[PACE_CH];
   __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
   __shared__ double rhs[PACE_KMAX];
@@ -145,16 +343,8 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
   const int tid = threadIdx.x;
   const int64_t P = g.P;
   const int nmat = k * (k + 1) / 2, nacc = nmat + k;
-  if (tid == 0)
-    for (int r = 0, e = 0; r < k; ++r)
-      for (int c = r; c < k; ++c, ++e) {
-        tri_r[e] = (unsigned char)r;
-        tri_c[e] = (unsigned char)c;
-      }
   const bool fast = design == FPCA_COMMON_GRID && Lcg && cg_ok && cg_ok[0] == 1;
-  if (fast)
-    for (int e = tid; e < k * k; e += PACE_THREADS) Lc[e / k][e % k] = Lcg[e];
-  __syncthreads();
+  bool built = false;  // the triangle's index tables, formed at the first curve this workgroup solves
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     int64_t a, b;
     if (design == FPCA_IRREGULAR) {
@@ -164,42 +354,21 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
       a = i * P;
       b = a + P;
     }
+    // with the shared factor, k_pace_cg_rhs has solved every complete curve
+    // and marked the others with a NaN first score
     if (fast) {
-      // a curve observed at every node uses the shared factor: only
-      // Phi^T (Y_i - mu) is formed (strided per thread, then the waves in order)
-      bool missing = false;
-      for (int64_t p = tid; p < P; p += PACE_THREADS) missing |= !isfinite(double(y[a + p]));
-      if (!__syncthreads_or(missing)) {
-        double part[PACE_KMAX];
-#pragma unroll
-        for (int l = 0; l < PACE_KMAX; ++l) part[l] = 0.0;
-        for (int64_t p = tid; p < P; p += PACE_THREADS) {
-          const double ycv = double(y[a + p]) - double(mu[p]);
-#pragma unroll
-          for (int l = 0; l < PACE_KMAX; ++l)
-            if (l < k) part[l] += double(efuns[int64_t(l) * P + p]) * ycv;
-        }
-        // constant indices throughout, so part[] stays in registers
-#pragma unroll
-        for (int l = 0; l < PACE_KMAX; ++l) {
-          double v = part[l];
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          if ((tid & 63) == 0 && l < k) red[tid >> 6][l] = v;
-        }
-        __syncthreads();
-        if (tid < k) {
-          double v = 0.0;
-          for (int w = 0; w < PACE_THREADS / 64; ++w) v += red[w][tid];
-          rhs[tid] = dg.v[tid] >= 0.0 ? v : 0.0;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          chol_solve(Lc, rhs, k);
-          for (int l = 0; l < k; ++l) scores[i * k + l] = T(rhs[l]);
-        }
-        __syncthreads();  // rhs and red are reused by the next curve
-        continue;
-      }
+      const double s0 = double(scores[i * k]);
+      if (s0 == s0) continue;  // uniform: every thread reads the same value
+    }
+    if (!built) {
+      if (tid == 0)
+        for (int r = 0, e = 0; r < k; ++r)
+          for (int c = r; c < k; ++c, ++e) {
+            tri_r[e] = (unsigned char)r;
+            tri_c[e] = (unsigned char)c;
+          }
+      __syncthreads();
+      built = true;
     }
     double acc[PACE_ACC];
 #pragma unroll
@@ -307,10 +476,26 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
     Carver cv{static_cast<char *>(fixed ? fixed : ctx->ws), 0, fixed ? PACE_SCRATCH_BYTES : ctx->ws_size};
     double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
     int *okf = cv.take<int>(1);
-    hipLaunchKernelGGL(k_pace_cg_prep<T>, dim3(1), dim3(PACE_THREADS), 0, ctx->stream, g.P, efuns, k, dg, L, okf);
+    // vector loads when every row starts on a 16-byte boundary
+    const bool vec = g.P % 4 == 0 && (reinterpret_cast<uintptr_t>(efuns) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_pace_cg_prep<T, true>), dim3(1), dim3(CG_THREADS), 0, ctx->stream, g.P, efuns, k, dg, L,
+                         okf);
+    else
+      hipLaunchKernelGGL((k_pace_cg_prep<T, false>), dim3(1), dim3(CG_THREADS), 0, ctx->stream, g.P, efuns, k, dg,
+                         L, okf);
     FPCA_LAUNCH_CHECK("pace_cg_prep");
     Lcg = L;
     cg_ok = okf;
+    const dim3 rgrid(unsigned((n + RH_CURVES - 1) / RH_CURVES));
+    if (vec)
+      hipLaunchKernelGGL((k_pace_cg_rhs<T, true>), rgrid, dim3(RH_THREADS), 0, ctx->stream, n, g.P, y, mu, efuns, k,
+                         dg, Lcg, cg_ok, scores);
+    else
+      hipLaunchKernelGGL((k_pace_cg_rhs<T, false>), rgrid, dim3(RH_THREADS), 0, ctx->stream, n, g.P, y, mu, efuns, k,
+                         dg, Lcg, cg_ok, scores);
+    FPCA_LAUNCH_CHECK("pace_cg_rhs");
   }
   const unsigned blocks = unsigned(n < 65536 ? n : 65536);
   hipLaunchKernelGGL(k_pace<T>, dim3(blocks), dim3(PACE_THREADS), 0, ctx->stream, g, n, design, offsets, t, y, mu,
