@@ -205,14 +205,28 @@ __global__ __launch_bounds__(256) void k_lr_partial(CovGeo g, int r, const doubl
   }
 }
 
-__global__ void k_lr_reduce(int64_t nblk, int rows, int r, const double *__restrict__ part, double *__restrict__ tot) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= int64_t(rows) * r) return;
-  const int64_t j = e / r;
-  const int c = int(e - j * r);
+// tot[j][c] = sum over the row blocks of part[b][j][c]: one workgroup per row
+// j; thread (group g, column c) adds blocks g, g + 4, ... (eight loads in
+// flight), then the four groups are added in order.
+__global__ __launch_bounds__(256) void k_lr_reduce(int64_t nblk, int rows, int r, const double *__restrict__ part,
+                                                   double *__restrict__ tot) {
+  __shared__ double gs[4][64];
+  const int j = blockIdx.x, c = threadIdx.x & 63, g = threadIdx.x >> 6;
   double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += part[(b * rows + j) * 64 + c];
-  tot[j * 64 + c] = s;
+  if (c < r) {
+    int64_t b = g;
+    for (; b + 28 < nblk; b += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[((b + 4 * u) * rows + j) * 64 + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < nblk; b += 4) s += part[(b * rows + j) * 64 + c];
+  }
+  gs[g][c] = s;
+  __syncthreads();
+  if (g == 0 && c < r) tot[int64_t(j) * 64 + c] = ((gs[0][c] + gs[1][c]) + gs[2][c]) + gs[3][c];
 }
 
 // out[s][c] = (1/n) sum_i (L[s][i] U[i][c] - B[s][i] V[i][c]) - mu[s] m[c]
@@ -966,7 +980,7 @@ int covop_apply_internal(fpca_covop_s *op, int r, const double *X, double *out) 
   hipLaunchKernelGGL(k_lr_partial, dim3(unsigned(op->lr_blocks), unsigned((op->n + 63) / 64)), dim3(256), 0,
                      ctx->stream, g, r, X, op->Ln, op->Bn, op->mu, op->lr_part);
   FPCA_LAUNCH_CHECK("covop lr partial");
-  hipLaunchKernelGGL(k_lr_reduce, dim3(nb256(int64_t(rows) * r)), dim3(256), 0, ctx->stream, op->lr_blocks, rows, r,
+  hipLaunchKernelGGL(k_lr_reduce, dim3(unsigned(rows)), dim3(256), 0, ctx->stream, op->lr_blocks, rows, r,
                      op->lr_part, op->lr_tot);
   FPCA_LAUNCH_CHECK("covop lr reduce");
   hipLaunchKernelGGL(k_lr_out, dim3(unsigned((op->P + 63) / 64)), dim3(256), 0, ctx->stream, g, r, op->Ln, op->Bn,
