@@ -163,6 +163,33 @@ def cv_d3_timing(h, torch, F):
             "node_solves_per_s": sc.size * P * P / t_cv}
 
 
+def fits_timing(h, torch, F):
+    """The whole hot path (bin mean, smooth mean, bin pairs, smooth covariance,
+    randomized eig) on the other two FPCA workloads: d=1 FP64 curves (mean grid
+    101, covariance 51 x 51) and d=2 irregular FP32 surfaces (32^2 grid,
+    covariance 32^4 nodes); median of 5 fits after a warm-up."""
+    from fpca_synth import make_c1, make_c2
+    from paper_1510_04439_amd import pipeline as PL
+    log("end-to-end fits, d=1 and d=2 irregular")
+    res = {}
+    for name, ds in (("d1_fp64_101_51", make_c1()), ("d2_irregular_32x32", make_c2())):
+        dd = PL.to_device(ds)
+        bufs = PL.alloc(dd, ds.k)
+        args = (ds.h_mean, ds.h_cov, ds.k, ds.oversample, ds.power_iters, ds.rp_seed)
+        PL.fit(h, dd, bufs, *args)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            PL.fit(h, dd, bufs, *args)  # returns after the eigenvalues reached the host
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        P = int(np.prod(ds.M_cov))
+        res[name] = {"fit_ms": float(np.median(ts)) * 1e3, "observations": int(len(ds.y)) if ds.t is not None else int(ds.y.size),
+                     "curves": ds.n, "cov_nodes": P * P, "evals_top3": [float(v) for v in bufs.evals[:3]]}
+    return res
+
+
 def f2_timing(h, torch, F):
     """Simulation II's shape (d=3, 64^3 grid, n=100 complete curves, h=0.1):
     the smoothed covariance on 64^6 = 6.9e10 nodes (275 GB in FP32) is never
@@ -313,6 +340,7 @@ def main():
     ap.add_argument("--no-hselect", action="store_true", help="skip the surrogate-versus-CV timing")
     ap.add_argument("--no-f1", action="store_true", help="skip the noise-variance, PACE and reconstruction timing")
     ap.add_argument("--no-f2", action="store_true", help="skip the covariance-operator (64^3) timing")
+    ap.add_argument("--no-fits", action="store_true", help="skip the d=1 and d=2 irregular end-to-end fits")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
@@ -474,6 +502,7 @@ def main():
     if not args.no_cv_d3:
         out["cv_d3"] = cv_d3_timing(h, torch, F)
     out["f2"] = None if args.no_f2 else f2_timing(h, torch, F)
+    out["fits"] = None if args.no_fits else fits_timing(h, torch, F)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         G_host = bufs.G.cpu().numpy().astype(np.float64)

@@ -143,6 +143,34 @@ def test_covop_sampled_columns_wide_band(torch, F, h):
             assert normwise_rel(got[:, j], ref) < 1e-10
 
 
+def test_covop_widest_d3_window(torch, F, h):
+    """d = 3 at the largest window the operator takes (6 grid steps in every
+    coordinate: shared-node boxes of 16 nodes per coordinate, the tile-pair
+    limit): one column of the covariance against the oracle."""
+    M, hb = (13, 13, 13), 0.5
+    _say(f"covop widest window M={M} h={hb}")
+    rng = np.random.default_rng(8)
+    P = int(np.prod(M))
+    Y = _curves(rng, M, 12)
+    mu = Y.mean(0)
+    _, _, C, G = oracle.bin_common_grid(Y)
+    q = P // 2 + 7
+    E = np.zeros((P, 1))
+    E[q, 0] = 1.0
+    op = F.CovOp(h, F.Grid(M), dev(torch, Y), dev(torch, mu), hb, 0)
+    try:
+        out = torch.empty(P, 1, dtype=torch.float64, device="cuda:0")
+        op.apply(dev(torch, E), out)
+        h.sync()
+        got = host(out)[:, 0]
+    finally:
+        op.close()
+    p = np.arange(P)
+    rb, _ = oracle.smooth_cov_raw(M, hb, C, G, np.concatenate([p * P + q, q * P + p]))
+    ref = 0.5 * (rb[:P] + rb[P:]) - mu * mu[q]
+    assert normwise_rel(got, ref) < 1e-10
+
+
 @pytest.mark.parametrize("M,hb", [((70,), 0.12), ((20, 18), 0.15), ((9, 8, 6), (0.3, 0.3, 0.45))])
 def test_covop_eig_matches_oracle(torch, F, h, M, hb):
     """fpca_eig_covop against the oracle's randomized eigendecomposition of the
