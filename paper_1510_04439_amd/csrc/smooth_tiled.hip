@@ -23,9 +23,11 @@
 //            lands in LDS as the final moments of M_1 x QB nodes, then one
 //            lane per node solves the (2d+1) x (2d+1) system in FP64
 //            (wls_b0) and writes b0 (and the status).
-//  score     (cross-validation) tile pairs of b0 symmetrized, masked and
-//            scored against the held-out fold: sum Q_f - 2 G_f g + C_f g^2,
-//            FP64 partial per task.
+//  score     (cross-validation) tile pairs of b0, masked and scored against
+//            the held-out fold: sum Q_f - 2 G_f g + C_f g^2, FP64 partial per
+//            task. C and G are symmetric, so a score needs b0 at p <= q only
+//            (s_1 <= t_1): in cross-validation stage W solves those nodes and
+//            stage S skips the rows no such node reads.
 //  finish    the partials of a job summed in a fixed order.
 //
 // The queue is a list of segments (job, stage, task count) in rounds: round r
@@ -82,10 +84,11 @@ typedef __attribute__((address_space(3))) double LDbl;
 constexpr int TQ_KC = 8;  // window reads issued together
 constexpr int TQ_U = 8;   // global reads per thread issued before their LDS stores
 
-// dst[e] = get(e) for e < n: every thread issues TQ_U independent reads before
-// storing them, so a workgroup keeps TQ_U * TQ_THREADS reads in flight.
-template <typename GET>
-__device__ inline void stage_to_lds(__attribute__((address_space(3))) double *dst, int n, GET get) {
+// dst[at(e)] = get(e) for e < n (at(e) = e by default): every thread issues
+// TQ_U independent reads before storing them, so a workgroup keeps
+// TQ_U * TQ_THREADS reads in flight.
+template <typename GET, typename DST>
+__device__ inline void stage_to_lds(__attribute__((address_space(3))) double *dst, int n, GET get, DST at) {
   for (int b = threadIdx.x; b < n; b += TQ_U * TQ_THREADS) {
     double v[TQ_U];
 #pragma unroll
@@ -96,9 +99,13 @@ __device__ inline void stage_to_lds(__attribute__((address_space(3))) double *ds
 #pragma unroll
     for (int u = 0; u < TQ_U; ++u) {
       const int e = b + u * TQ_THREADS;
-      if (e < n) dst[e] = v[u];
+      if (e < n) dst[at(e)] = v[u];
     }
   }
+}
+template <typename GET>
+__device__ inline void stage_to_lds(__attribute__((address_space(3))) double *dst, int n, GET get) {
+  stage_to_lds(dst, n, get, [](int e) { return e; });
 }
 
 // q = x / d and r = x % d for 0 <= x < 2^22 and a small divisor d, from a
@@ -168,12 +175,17 @@ __device__ inline void window_acc(LD ld, int x0, int n, int R, CDbl *t0, CDbl *t
 // lanes take consecutive lines. `ld(i)` reads the source at element offset i,
 // `st(j, i, v)` stores output j at offset i (same offsets in the destination).
 template <int ax, typename LD, typename STF>
-__device__ inline void pass_axis(const Blk &bk, CDbl *taps, int R, int e0, int nj, LD ld, STF st) {
+__device__ inline void pass_axis(const Blk &bk, CDbl *taps, int R, int e0, int nj, LD ld, STF st, int lo = 0) {
+  // lo > 0 limits the pass to axis-0 indices >= lo: for ax = 0 the outputs
+  // from the segment holding lo on (lo a multiple of TQ_SEG), otherwise the
+  // lines whose axis-0 index is >= lo
   constexpr int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
   const int n2 = bk.n[o2];
-  const int nl = bk.n[o1] * n2;
+  const int l1lo = ax == 0 ? 0 : lo;
+  const int nl = (bk.n[o1] - l1lo) * n2;
   const int n = bk.n[ax];
-  const int nseg = (n + TQ_SEG - 1) / TQ_SEG;
+  const int sglo = ax == 0 ? lo / TQ_SEG : 0;
+  const int nseg = (n + TQ_SEG - 1) / TQ_SEG - sglo;
   const int W = 2 * R + 1;
   const long long sx = bk.s[ax];
   const float rnl = 1.0f / float(nl), rn2 = 1.0f / float(n2);
@@ -181,8 +193,9 @@ __device__ inline void pass_axis(const Blk &bk, CDbl *taps, int R, int e0, int n
     int sg, line, l1, l2;
     fast_divmod(it, nl, rnl, sg, line);
     fast_divmod(line, n2, rn2, l1, l2);
+    l1 += l1lo;
     const long long base = (long long)l1 * bk.s[o1] + (long long)l2 * bk.s[o2];
-    const int x0 = sg * TQ_SEG;
+    const int x0 = (sg + sglo) * TQ_SEG;
     double acc[3][TQ_SEG];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -231,6 +244,17 @@ __device__ void stage_t(const TArgs &a, const TJob &jb, int p, LDbl *lds) {
   bk.s[2] = 1;
   bk.s[1] = bk.n[2];
   bk.s[0] = (long long)bk.n[1] * bk.n[2];
+  // Cross-validation (d = 3): stage S reads row p (s_1 = p / PR) only in
+  // column blocks whose last t_1 is >= s_1 - R, i.e. columns with
+  // t_1 >= t1_lo (QB divides PR = M_2 M_3 here); the t_1 pass forms those from
+  // the segment holding t1_lo on (t1_out) and reads t-slabs t_1 >= t1_in,
+  // the only ones the t_3 and t_2 passes need to form.
+  int t1_out = 0, t1_in = 0;
+  if (d == 3 && a.cv && (P / jb.M[0]) % a.qb == 0) {
+    const int t1_lo = max(0, int(p / (P / jb.M[0])) - jb.R[0]);
+    t1_out = (t1_lo / TQ_SEG) * TQ_SEG;
+    t1_in = max(0, t1_out - jb.R[0]);
+  }
   int xi = 0;
   for (int fam = 0; fam < 2; ++fam) {
     const int md = 2 - fam;
@@ -251,7 +275,8 @@ __device__ void stage_t(const TArgs &a, const TJob &jb, int p, LDbl *lds) {
       xi += nj;
     } else {
       for (int ec = 0; ec <= md; ++ec) {
-        pass_axis<2>(bk, tap_ptr(a, jb, kc), jb.R[kc], ec, 1, ldg, [&](int, long long i, double v) { L1[i] = v; });
+        pass_axis<2>(bk, tap_ptr(a, jb, kc), jb.R[kc], ec, 1, ldg, [&](int, long long i, double v) { L1[i] = v; },
+                     t1_in);
         __syncthreads();
         if constexpr (d == 2) {
           const int nj = md - ec + 1;
@@ -262,11 +287,11 @@ __device__ void stage_t(const TArgs &a, const TJob &jb, int p, LDbl *lds) {
         } else {
           for (int eb = 0; eb <= md - ec; ++eb) {
             pass_axis<1>(bk, tap_ptr(a, jb, 1), jb.R[1], eb, 1, [&](long long i) { return L1[i]; },
-                [&](int, long long i, double v) { L2[i] = v; });
+                [&](int, long long i, double v) { L2[i] = v; }, t1_in);
             __syncthreads();
             const int nj = md - ec - eb + 1;
             pass_axis<0>(bk, tap_ptr(a, jb, 0), jb.R[0], 0, nj, [&](long long i) { return L2[i]; },
-                [&](int j, long long i, double v) { X[(long long)(xi + j) * P * P + p * P + i] = v; });
+                [&](int j, long long i, double v) { X[(long long)(xi + j) * P * P + p * P + i] = v; }, t1_out);
             xi += nj;
             __syncthreads();
           }
@@ -287,6 +312,9 @@ __device__ void stage_s(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
   const int a1 = task / nqb, q0 = (task % nqb) * QB;
   const int qn = min(QB, jb.P - q0);
   const int PR = jb.P / jb.M[0];  // s-positions per s_1 index
+  // cross-validation scores only need nodes p <= q (s_1 <= t_1): the s_1 pass
+  // of stage W reads this row only for outputs within R of it
+  if (a.cv && a1 > (q0 + qn - 1) / PR + jb.R[0]) return;
   LDbl *L0 = lds;
   LDbl *L1 = L0 + (long long)PR * QB;
   const double *X = slot_x(a, jb.slot);
@@ -353,26 +381,40 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
   const int W = 2 * jb.R[0] + 1;
   const int R = jb.R[0];
   CDbl *tp = tap_ptr(a, jb, 0);
-  const int nseg = (M1 + TQ_SEG - 1) / TQ_SEG;
-  const int per_y = QB * nseg;
-  const float rper = 1.0f / float(per_y), rqb = 1.0f / float(QB), rpen = 1.0f / float(M1 * QB);
+  const float rqb = 1.0f / float(QB);
   const int r_end = min(PR, (pbi + 1) * jb.pb);
   (void)npb;
   const int pen = M1 * QB;
+  // Cross-validation scores only need nodes p <= q, so s_1 <= t_1 <= n_out - 1
+  // (the last t_1 of the column block): the s_1 pass forms outputs below
+  // n_out from input rows below n_in (beyond them the line is read as zero,
+  // which those outputs never reach); smoothing needs every node.
+  const int n_out = a.cv ? min(M1, (q0 + qn - 1) / PR + 1) : M1;
+  const int n_in = min(M1, n_out + R);
+  const int pen_in = n_in * QB;
+  const float rpen_in = 1.0f / float(pen_in);
+  const int nseg_out = (n_out + TQ_SEG - 1) / TQ_SEG;
+  const int per_out = QB * nseg_out;
+  const float rper_out = 1.0f / float(per_out);
   for (int r = pbi * jb.pb; r < r_end; ++r) {
     __syncthreads();
-    // stage the pencils of every Y array at s-position (., r), all loads in flight
-    stage_to_lds(Ys, ny * pen, [&](int e) {
+    // stage the pencils (input rows below n_in) of every Y array at
+    // s-position (., r), all loads in flight
+    stage_to_lds(Ys, ny * pen_in, [&](int e) {
       int y, rem, a1, c;
-      fast_divmod(e, pen, rpen, y, rem);
+      fast_divmod(e, pen_in, rpen_in, y, rem);
       fast_divmod(rem, QB, rqb, a1, c);
       return c < qn ? Y[(long long)y * P * P + ((long long)a1 * PR + r) * P + q0 + c] : 0.0;
+    }, [&](int e) {
+      int y, rem;
+      fast_divmod(e, pen_in, rpen_in, y, rem);
+      return y * pen + rem;
     });
     __syncthreads();
     // s_1 pass of every Y array at s-position (., r), columns q0..q0+qn
-    for (int it = threadIdx.x; it < ny * per_y; it += TQ_THREADS) {
+    for (int it = threadIdx.x; it < ny * per_out; it += TQ_THREADS) {
       int y, rem, sg, c;
-      fast_divmod(it, per_y, rper, y, rem);
+      fast_divmod(it, per_out, rper_out, y, rem);
       fast_divmod(rem, QB, rqb, sg, c);
       const int fam = (d == 1) ? a.tabs->x_fam[y] : a.tabs->y_fam[y];
       const int deg = (d == 1) ? a.tabs->x_deg[y] : a.tabs->y_deg[y];
@@ -385,11 +427,11 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
       for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int q = 0; q < TQ_SEG; ++q) acc[j][q] = 0.0;
-      window_acc([&](int xc) { return src[xc * sx]; }, x0, M1, R, tp, tp + W, tp + 2 * W, nj, acc);
+      window_acc([&](int xc) { return src[xc * sx]; }, x0, n_in, R, tp, tp + W, tp + 2 * W, nj, acc);
 #pragma unroll
       for (int q = 0; q < TQ_SEG; ++q) {
         const int xo = x0 + q;
-        if (xo < M1) {
+        if (xo < n_out) {
 #pragma unroll
           for (int j = 0; j < 3; ++j)
             if (j < nj) F[((long long)a.tabs->y_mom[y][j] * M1 + xo) * QB + c] = acc[j][q];
@@ -398,7 +440,7 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
     }
     __syncthreads();
     // one lane per node (a1, c): the FP64 solve
-    for (int e = threadIdx.x; e < M1 * QB; e += TQ_THREADS) {
+    for (int e = threadIdx.x; e < n_out * QB; e += TQ_THREADS) {
       const int a1 = e / QB, c = e % QB;
       if (c >= qn) continue;
       double m[NM];
@@ -428,16 +470,17 @@ __device__ void stage_w(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
 }
 
 // ------------------------------------------------------------------ score
-// Tile pairs (I, J), I <= J, of the P x P grid in TQ_TILE x TQ_TILE tiles; g is b0
-// symmetrized (for leave-one-out jobs the node's own b0), 0 outside the mask
-// and where b0 is NaN (an empty window).
+// Tile pairs (I, J), I <= J, of the P x P grid in TQ_TILE x TQ_TILE tiles.
+// Stage W solved the nodes p <= q only (C and G are symmetric, so the fit at
+// (q, p) is the fit at (p, q) up to rounding): g(p, q) = b0(min, max), read
+// from tile (I, J) alone (for leave-one-out jobs too: the node's own bin is
+// the same at both), 0 outside the mask and where b0 is NaN (an empty window).
 template <typename T>
 __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, LDbl *lds) {
   const int P = jb.P;
   const int nt = (P + TQ_TILE - 1) / TQ_TILE;
-  LDbl *A = lds;                           // [TQ_TILE][TQ_TILE+1]: b0 of tile (I, J)
-  LDbl *B = A + TQ_TILE * (TQ_TILE + 1);  // [TQ_TILE][TQ_TILE+1]: b0 of tile (J, I)
-  LDbl *red = B + TQ_TILE * (TQ_TILE + 1);  // [TQ_THREADS / 64] wave sums
+  LDbl *A = lds;                            // [TQ_TILE][TQ_TILE+1]: b0 of tile (I, J)
+  LDbl *red = A + TQ_TILE * (TQ_TILE + 1);  // [TQ_THREADS / 64] wave sums
   const T *Gh = static_cast<const T *>(slot_g(a, jb.slot));
   const T *Q = static_cast<const T *>(jb.Qf);
   const T *G = static_cast<const T *>(jb.Gf);
@@ -456,7 +499,7 @@ __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, L
     constexpr int EPT = TQ_TILE * TQ_TILE / TQ_THREADS;  // elements of a tile per thread
     static_assert(EPT * TQ_THREADS == TQ_TILE * TQ_TILE, "tile must split evenly over the workgroup");
     // every read of this tile pair is issued before any of them is used
-    double va[EPT], vb[EPT], q1[EPT], g1[EPT], w1[EPT], q2[EPT], g2[EPT], w2[EPT];
+    double va[EPT], q1[EPT], g1[EPT], w1[EPT], q2[EPT], g2[EPT], w2[EPT];
     bool in1[EPT], in2[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
@@ -464,7 +507,6 @@ __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, L
       const int rr = e / TQ_TILE, cc = e % TQ_TILE;
       const bool ia = r0 + rr < P && c0 + cc < P, ib = c0 + rr < P && r0 + cc < P;
       va[u] = ia ? double(Gh[(long long)(r0 + rr) * P + c0 + cc]) : 0.0;
-      vb[u] = ib ? double(Gh[(long long)(c0 + rr) * P + r0 + cc]) : 0.0;
       // held-out arrays at (p, q) = (r0 + rr, c0 + cc) and at the mirror (c0 + rr, r0 + cc)
       in1[u] = ia;
       const long long o1 = (long long)(r0 + rr) * P + c0 + cc;
@@ -481,29 +523,26 @@ __device__ void stage_score(const TArgs &a, const TJob &jb, int job, int task, L
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = threadIdx.x + u * TQ_THREADS;
-      const int rr = e / TQ_TILE, cc = e % TQ_TILE;
-      A[rr * (TQ_TILE + 1) + cc] = va[u];
-      B[rr * (TQ_TILE + 1) + cc] = vb[u];
+      A[(e / TQ_TILE) * (TQ_TILE + 1) + e % TQ_TILE] = va[u];
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = threadIdx.x + u * TQ_THREADS;
       const int rr = e / TQ_TILE, cc = e % TQ_TILE;
-      // (p, q) in tile (I, J): g = (b(p,q) + b(q,p)) / 2 = (A[rr][cc] + B[cc][rr]) / 2
+      // (p, q) in tile (I, J): p < q off the diagonal tile; on it the smaller
+      // index's row holds the solved node
       if (in1[u]) {
         const int p = r0 + rr, q = c0 + cc;
-        double g = jb.loo ? A[rr * (TQ_TILE + 1) + cc]
-                          : 0.5 * (A[rr * (TQ_TILE + 1) + cc] + B[cc * (TQ_TILE + 1) + rr]);
+        double g = (I != J || rr <= cc) ? A[rr * (TQ_TILE + 1) + cc] : A[cc * (TQ_TILE + 1) + rr];
         if (mask && (!mask[p] || !mask[q])) g = 0.0;
         if (g != g) g = 0.0;
         s += q1[u] - 2.0 * g1[u] * g + w1[u] * g * g;
       }
-      // (q, p) = (c0 + rr, r0 + cc): g = (B[rr][cc] + A[cc][rr]) / 2
+      // (q, p) = (c0 + rr, r0 + cc) in tile (J, I), I < J: the node (r0 + cc, c0 + rr) of tile (I, J)
       if (in2[u]) {
         const int q = c0 + rr, p = r0 + cc;
-        double g = jb.loo ? B[rr * (TQ_TILE + 1) + cc]
-                          : 0.5 * (B[rr * (TQ_TILE + 1) + cc] + A[cc * (TQ_TILE + 1) + rr]);
+        double g = A[cc * (TQ_TILE + 1) + rr];
         if (mask && (!mask[p] || !mask[q])) g = 0.0;
         if (g != g) g = 0.0;
         s += q2[u] - 2.0 * g2[u] * g + w2[u] * g * g;
@@ -717,7 +756,7 @@ size_t lds_bytes(int d, int Pmax, int M1max, int PRmax, int qb) {
   size_t t = size_t(d + 0) * size_t(Pmax);  // L0 (+ L1, L2)
   size_t s = (d == 3 ? 2 : (d == 2 ? 1 : 0)) * size_t(PRmax) * qb;
   size_t w = size_t(NM + NY) * M1max * qb;
-  size_t sc = 2 * TQ_TILE * (TQ_TILE + 1) + TQ_THREADS;
+  size_t sc = TQ_TILE * (TQ_TILE + 1) + TQ_THREADS;
   return 8 * std::max(std::max(t, s), std::max(w, sc));
 }
 
