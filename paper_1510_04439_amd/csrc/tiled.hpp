@@ -15,6 +15,7 @@ constexpr int TQ_MAXY = 27;  // stage-S arrays (d = 3)
 constexpr int TQ_NSTAGE = 5;
 constexpr int TQ_TILE = 32;   // score tile
 constexpr int TQ_MAXSLOT = 3;
+constexpr int TQ_CHUNK_MAX = 16;  // queue tasks taken per atomic, at most
 constexpr size_t TQ_LDS_MAX = 160 * 1024 - 256;  // dynamic LDS per workgroup (static LDS is below 256 B)
 enum { TQ_T = 0, TQ_S = 1, TQ_W = 2, TQ_SC = 3, TQ_FIN = 4 };
 
@@ -60,6 +61,7 @@ struct TArgs {
   double *scores;  // [njobs]
   int cv;
   int qb;
+  int chunk;  // queue tasks taken per atomic
   const double *taps;  // tap table: per job and coordinate, [e][m + R]
   long long spin_limit;
   int nx, ny;
