@@ -328,17 +328,34 @@ __device__ void stage_s(const TArgs &a, const TJob &jb, int task, LDbl *lds) {
   bk.s[0] = (long long)bk.n[1] * QB;
   const long long prow = (long long)a1 * PR;  // first s-node of this s_1 index
   const float rqb = 1.0f / float(QB);
+  // The block of array x + 1 is read into registers (TQ_SPF per thread, every
+  // load issued at clamped addresses, then masked) while the passes of array
+  // x run; PR * QB <= TQ_SPF * TQ_THREADS (checked by the planner).
+  double pf[TQ_SPF];
+  auto fetch = [&](int x) {
+    const double *Xx = X + (long long)x * P * P;
+#pragma unroll
+    for (int u = 0; u < TQ_SPF; ++u) {
+      const int e = threadIdx.x + u * TQ_THREADS;
+      int r, c;
+      fast_divmod(min(e, PR * QB - 1), QB, rqb, r, c);
+      const bool ok = e < PR * QB && c < qn;
+      const double v = Xx[(prow + r) * P + q0 + min(c, qn - 1)];
+      pf[u] = ok ? v : 0.0;
+    }
+  };
+  fetch(0);
   int yi = 0;
   for (int x = 0; x < a.nx; ++x) {
     const int md = (2 - a.tabs->x_fam[x]) - a.tabs->x_deg[x];
     __syncthreads();
-    const double *Xx = X + (long long)x * P * P;
-    stage_to_lds(L0, PR * QB, [&](int e) {
-      int r, c;
-      fast_divmod(e, QB, rqb, r, c);
-      return c < qn ? Xx[(prow + r) * P + q0 + c] : 0.0;
-    });
+#pragma unroll
+    for (int u = 0; u < TQ_SPF; ++u) {
+      const int e = threadIdx.x + u * TQ_THREADS;
+      if (e < PR * QB) L0[e] = pf[u];
+    }
     __syncthreads();
+    if (x + 1 < a.nx) fetch(x + 1);
     // element (r, c) of the block -> Y offset (prow + r) * P + q0 + c
     auto gidx = [&](long long i) { return (prow + i / QB) * P + q0 + (i % QB); };
     if constexpr (d == 2) {
@@ -850,6 +867,8 @@ int tiled_plan(fpca_context *ctx, const std::vector<TiledJob> &jobs, bool cv, co
     t.slot = j % NS;
     t.prev = j >= NS ? j - NS : -1;
     const int PR = P / t.M[0];
+    if (int64_t(PR) * qb > int64_t(TQ_SPF) * TQ_THREADS)
+      return set_error(FPCA_ERR_UNSUPPORTED, "tiled smoother: %d s-positions x %d columns per stage-S block", PR, qb);
     const int nqb = (P + qb - 1) / qb;
     t.pb = std::max(1, (2048 + t.M[0] * qb - 1) / (t.M[0] * qb));
     t.pb = std::min(t.pb, PR);

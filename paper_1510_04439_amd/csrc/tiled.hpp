@@ -16,6 +16,7 @@ constexpr int TQ_NSTAGE = 5;
 constexpr int TQ_TILE = 32;   // score tile
 constexpr int TQ_MAXSLOT = 3;
 constexpr int TQ_CHUNK_MAX = 16;  // queue tasks taken per atomic, at most
+constexpr int TQ_SPF = 8;    // stage-S values prefetched per thread
 constexpr size_t TQ_LDS_MAX = 160 * 1024 - 256;  // dynamic LDS per workgroup (static LDS is below 256 B)
 enum { TQ_T = 0, TQ_S = 1, TQ_W = 2, TQ_SC = 3, TQ_FIN = 4 };
 
