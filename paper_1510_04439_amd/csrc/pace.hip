@@ -73,30 +73,29 @@ __device__ inline void load4(const double *p, double *o) {
   const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
   o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
 }
-constexpr int CG_THREADS = 1024;  // 16 wavefronts
+constexpr int CG_THREADS = 1024;  // 16 wavefronts (the inverse)
+constexpr int CG_NG = 16;         // workgroups of the shared matrix's partial sums
+constexpr int CG_GT = 256;        // their threads (4 wavefronts)
 constexpr int MB = 8;             // MFMA steps (4 nodes each) whose operands are loaded together
 
-// Common grid: the factor of Phi^T Phi + sigma^2 Lambda^{-1} over all P nodes,
-// shared by every curve observed at all of them. One workgroup: wavefront w
-// takes a contiguous sixteenth of the nodes and accumulates the 16 x 16 tiles
-// (tr, tc) of Phi^T Phi with FP64 MFMA (16 x 16 x 4: lane l carries
-// Phi[16 tr + l % 16][node + l / 16] as the A operand and the same for tc as
-// the B operand), the operands of MB steps loaded before they are used; the
-// sixteen partial tiles are summed in a fixed order (waves 4g + w, g = 0..3,
-// into slot w, then the four slots); its inverse (below) goes to Lout.
+// Common grid: partial sums of Phi^T Phi over the P nodes, shared by every
+// curve observed at all of them. Workgroup b of CG_NG takes a contiguous
+// share of the nodes, each of its wavefronts a quarter of that, and
+// accumulates the 16 x 16 tiles (tr, tc) of Phi^T Phi with FP64 MFMA
+// (16 x 16 x 4: lane l carries Phi[16 tr + l % 16][node + l / 16] as the A
+// operand and the same for tc as the B operand), the operands of MB steps
+// loaded before they are used; the four wavefronts' tiles are summed in a
+// fixed order into part[b][tile] (tiles (0,0), (0,1), (1,1)).
 template <typename T, bool VEC>
-__global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int64_t P, const T *__restrict__ efuns, int k,
-                                                             PaceDiag dg, double *__restrict__ Lout,
-                                                             int *__restrict__ ok) {
-  __shared__ double part[4][2][2][256];
-  __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
-  __shared__ double Mb[PACE_KMAX][2 * PACE_KMAX];
+__global__ __launch_bounds__(CG_GT) void k_pace_cg_gram(int64_t P, const T *__restrict__ efuns, int k,
+                                                        double *__restrict__ part) {
+  __shared__ double red[4][3][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nt = k > 16 ? 2 : 1;
   const int row = lane & 15, kk = lane >> 4;
-  constexpr int NW = CG_THREADS / 64;
+  constexpr int NW = CG_NG * (CG_GT / 64);
   const int64_t per = ((P + NW * 4 * MB - 1) / (NW * 4 * MB)) * 4 * MB;  // nodes per wavefront
-  const int64_t n0 = wave * per, n1 = min(P, n0 + per);
+  const int64_t n0 = min(P, (int64_t(blockIdx.x) * (CG_GT / 64) + wave) * per), n1 = min(P, n0 + per);
   v4d d00 = {0, 0, 0, 0}, d01 = d00, d11 = d00;
   const bool r0 = row < k, r1 = 16 + row < k;
   const T *f0p = efuns + int64_t(r0 ? row : 0) * P;
@@ -138,29 +137,43 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int64_t P, const T 
       }
     }
   }
-  // D[i][j] of a tile sits in lane j + 16 (i % 4), element i / 4; waves
-  // 4g .. 4g + 3 add into the four slots in turn (g = 0 writes)
-  for (int g = 0; g < NW / 4; ++g) {
-    if ((wave >> 2) == g) {
-      const int w = wave & 3;
+  // D[i][j] of a tile sits in lane j + 16 (i % 4), element i / 4
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int e = (kk + 4 * v) * 16 + row;
-        part[w][0][0][e] = (g ? part[w][0][0][e] : 0.0) + d00[v];
-        part[w][0][1][e] = (g ? part[w][0][1][e] : 0.0) + d01[v];
-        part[w][1][1][e] = (g ? part[w][1][1][e] : 0.0) + d11[v];
-      }
-    }
-    __syncthreads();
+  for (int v = 0; v < 4; ++v) {
+    const int e = (kk + 4 * v) * 16 + row;
+    red[wave][0][e] = d00[v];
+    red[wave][1][e] = d01[v];
+    red[wave][2][e] = d11[v];
   }
+  __syncthreads();
+  for (int e = tid; e < 3 * 256; e += CG_GT) {
+    const int t = e / 256, ei = e % 256;
+    part[(int64_t(blockIdx.x) * 3 + t) * 256 + ei] = ((red[0][t][ei] + red[1][t][ei]) + red[2][t][ei]) + red[3][t][ei];
+  }
+}
+
+// Common grid: the shared matrix Phi^T Phi + sigma^2 Lambda^{-1} from the
+// CG_NG partial sums (added in workgroup order) and its inverse (below), to
+// Lout. One workgroup.
+__global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg, const double *__restrict__ part,
+                                                             double *__restrict__ Lout, int *__restrict__ ok) {
+  __shared__ double M0b[PACE_KMAX][2 * PACE_KMAX];
+  __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
+  __shared__ double Mb[PACE_KMAX][2 * PACE_KMAX];
+  const int tid = threadIdx.x;
   for (int e = tid; e < k * k; e += CG_THREADS) {
     const int r = e / k, c = e % k;
     // the upper tiles only: entry (r, c) of tile (1, 0) is (c, r) of tile (0, 1)
     const int rr = (r >> 4) > (c >> 4) ? c : r, cc = (r >> 4) > (c >> 4) ? r : c;
     const int tr = rr >> 4, tc = cc >> 4;
+    const int t = tr == 0 ? (tc == 0 ? 0 : 1) : 2;
     const int ei = (rr & 15) * 16 + (cc & 15);
+    double v[CG_NG];
+#pragma unroll
+    for (int b = 0; b < CG_NG; ++b) v[b] = part[(int64_t(b) * 3 + t) * 256 + ei];
     double sum = 0.0;
-    for (int w = 0; w < 4; ++w) sum += part[w][tr][tc][ei];
+#pragma unroll
+    for (int b = 0; b < CG_NG; ++b) sum += v[b];
     const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
     A[r][c] = (kr && kc) ? sum + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
   }
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int64_t P, const T 
   // symmetric positive definite when every kept component has lambda > 0;
   // the pivots are those of its LDL^T factorization, so a pivot <= 0 means it
   // is not: ok[0] = 0 (every curve then takes its own factorization).
-  double *M0 = &part[0][0][0][0], *M1 = &Mb[0][0];  // [PACE_KMAX][2 PACE_KMAX]
+  double *M0 = &M0b[0][0], *M1 = &Mb[0][0];  // [PACE_KMAX][2 PACE_KMAX]
   constexpr int LDM = 2 * PACE_KMAX;
   for (int e = tid; e < k * 2 * k; e += CG_THREADS) {
     const int r = e / (2 * k), j = e % (2 * k);
@@ -458,8 +471,10 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
   }
 }
 
-// Scratch of the common-grid design: the shared k x k factor and its flag.
-constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256;
+// Scratch of the common-grid design: the shared k x k inverse, its flag and
+// the partial sums of Phi^T Phi (8,192 + 256 + 98,304 bytes).
+constexpr size_t PACE_PART_BYTES = size_t(CG_NG) * 3 * 256 * sizeof(double);
+constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256 + PACE_PART_BYTES;
 
 // `fixed`: caller-provided scratch of PACE_SCRATCH_BYTES (the allocation-free
 // entry point), or NULL to carve it from the handle's arena.
@@ -476,15 +491,16 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
     Carver cv{static_cast<char *>(fixed ? fixed : ctx->ws), 0, fixed ? PACE_SCRATCH_BYTES : ctx->ws_size};
     double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
     int *okf = cv.take<int>(1);
+    double *gpart = cv.take<double>(PACE_PART_BYTES / sizeof(double));
     // vector loads when every row starts on a 16-byte boundary
     const bool vec = g.P % 4 == 0 && (reinterpret_cast<uintptr_t>(efuns) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
     if (vec)
-      hipLaunchKernelGGL((k_pace_cg_prep<T, true>), dim3(1), dim3(CG_THREADS), 0, ctx->stream, g.P, efuns, k, dg, L,
-                         okf);
+      hipLaunchKernelGGL((k_pace_cg_gram<T, true>), dim3(CG_NG), dim3(CG_GT), 0, ctx->stream, g.P, efuns, k, gpart);
     else
-      hipLaunchKernelGGL((k_pace_cg_prep<T, false>), dim3(1), dim3(CG_THREADS), 0, ctx->stream, g.P, efuns, k, dg,
-                         L, okf);
+      hipLaunchKernelGGL((k_pace_cg_gram<T, false>), dim3(CG_NG), dim3(CG_GT), 0, ctx->stream, g.P, efuns, k, gpart);
+    FPCA_LAUNCH_CHECK("pace_cg_gram");
+    hipLaunchKernelGGL(k_pace_cg_prep, dim3(1), dim3(CG_THREADS), 0, ctx->stream, k, dg, gpart, L, okf);
     FPCA_LAUNCH_CHECK("pace_cg_prep");
     Lcg = L;
     cg_ok = okf;
@@ -497,7 +513,9 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
                          dg, Lcg, cg_ok, scores);
     FPCA_LAUNCH_CHECK("pace_cg_rhs");
   }
-  const unsigned blocks = unsigned(n < 65536 ? n : 65536);
+  // grid-stride over the curves; on the common grid most of them are done
+  // (k_pace_cg_rhs solved them) and a workgroup only checks their marker
+  const unsigned blocks = unsigned(n < 2048 ? n : 2048);
   hipLaunchKernelGGL(k_pace<T>, dim3(blocks), dim3(PACE_THREADS), 0, ctx->stream, g, n, design, offsets, t, y, mu,
                      efuns, k, dg, Lcg, cg_ok, scores);
   FPCA_LAUNCH_CHECK("pace");

@@ -118,6 +118,28 @@ def test_pace_common_grid(torch, F, h, dt, mixed):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("M,k", [((16, 12), 17), ((9, 7), 20), ((64,), 19), ((10, 10), 24)])
+def test_pace_common_grid_components_past_16(torch, F, h, M, k, dt):
+    """k > 16 on the common grid: the components past the first 16 take the
+    second MFMA tile of the shared matrix and of the right-hand sides; node
+    loads by 16-byte vectors (P % 4 == 0) or one at a time; 40 complete
+    curves and one with a missing value (solved on its own)."""
+    _say(f"pace common grid M={M} k={k} {dt}")
+    rng = np.random.default_rng(k + len(M))
+    P = int(np.prod(M))
+    n = 41
+    Y = rng.standard_normal((n, P))
+    Y[13, P // 3] = np.nan
+    mu = rng.standard_normal(P)
+    efuns = rng.standard_normal((P, k)) / np.sqrt(P)
+    lam = np.geomspace(2.0, 0.02, k)
+    got, ref = _run(torch, F, h, M, F.FPCA_COMMON_GRID, None, None, Y, mu, efuns, lam, 0.1, dt)
+    tol = 1e-10 if dt == "f64" else 1e-5
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
 def test_pace_argument_errors(torch, F, h):
     _say("pace argument errors")
     M = (5,)
