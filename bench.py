@@ -332,8 +332,8 @@ def f1_timing(h, torch, F, dd, ds, b):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-d3", action="store_true", help="skip the d=3 batched-CV timing")
@@ -379,6 +379,27 @@ def main():
     bl = [PL.alloc(dd, ds.k, with_status=True, analytic_C=True) for _ in range(2)]
     bufs = bl[0]
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    # The pipelined steps split the chip: binning and smoothing on the lower
+    # three quarters of the CU mask, the latency-bound eigendecomposition on
+    # the top quarter (64 of 256 CUs, 8 per XCD: 0.88 against 0.95 ms per step
+    # unsplit; 32 or 96 CUs for it measured 1.25 and 0.97 ms). Plain streams
+    # when the runtime refuses the masks.
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    eig_cus = max(32, (ncu // 4) // 32 * 32)
+    raw_streams = []
+    try:
+        for lo, hi in ((0, ncu - eig_cus), (0, ncu - eig_cus), (ncu - eig_cus, ncu), (ncu - eig_cus, ncu)):
+            raw_streams.append(F.fpca_stream_create_cu_range(0, lo, hi))
+        s_stage = [torch.cuda.ExternalStream(r) for r in raw_streams[:2]]
+        s_eig = [torch.cuda.ExternalStream(r) for r in raw_streams[2:]]
+        split = f"binning and smoothing on CUs [0, {ncu - eig_cus}), eigendecomposition on [{ncu - eig_cus}, {ncu})"
+    except F.FpcaError:
+        for r in raw_streams:
+            F.fpca_stream_destroy(r)
+        raw_streams = []
+        s_stage = s_eig = streams
+        split = "one stream per step slot (CU masks refused)"
+    step_done = [torch.cuda.Event(), torch.cuda.Event()]
     gram_prec = F.FPCA_PREC_BF16X3 if args.gram_prec == "bf16x3" else F.FPCA_PREC_F32
 
     def stages(slot, ev=None):
@@ -407,14 +428,18 @@ def main():
 
     def run(nsteps):
         """nsteps pipelined steps: step i+1's binning and smoothing are queued before step i's
-        eigendecomposition, on the other slot's handle, buffers and stream."""
-        with torch.cuda.stream(streams[0]):
-            stages(0)
+        eigendecomposition, on the other slot's handle, buffers and streams; a step's
+        eigendecomposition waits for its own smoothing (an event between the two streams)."""
+        def stage_part(slot):
+            with torch.cuda.stream(s_stage[slot]):
+                stages(slot)
+                step_done[slot].record(s_stage[slot])
+        stage_part(0)
         for i in range(nsteps):
             if i + 1 < nsteps:
-                with torch.cuda.stream(streams[(i + 1) % 2]):
-                    stages((i + 1) % 2)
-            with torch.cuda.stream(streams[i % 2]):
+                stage_part((i + 1) % 2)
+            with torch.cuda.stream(s_eig[i % 2]):
+                s_eig[i % 2].wait_event(step_done[i % 2])
                 eig(i % 2)  # returns after this step's eigenvalues reached the host
 
     log("warmup")
@@ -483,8 +508,9 @@ def main():
                    "gram_prec": args.gram_prec},
         "stages_ms": stage_ms,
         "latency_ms_per_step": latency_ms,
-        "pipelining": "steps alternate over two handles, buffer sets and streams; step i+1's binning and "
-                      "smoothing run beside step i's eigendecomposition (stages_ms and latency from sequential steps)",
+        "pipelining": "steps alternate over two handles and buffer sets; step i+1's binning and smoothing run "
+                      "beside step i's eigendecomposition, " + split + " (stages_ms and latency from sequential "
+                      "steps on one unrestricted stream)",
         "smooth_cov_pts_per_s": nodes / (sc_ms / 1e3),
         "roofline": {"bound": "hbm", "kernel": "fpca_smooth_cov (k_tables, k_stage_t, k_stage_s)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -507,6 +533,9 @@ def main():
         log("cpu baseline (oracle on a sample)")
         G_host = bufs.G.cpu().numpy().astype(np.float64)
         out["cpu_baseline"] = cpu_baseline(ds, G_host, args.cpu_budget)
+    torch.cuda.synchronize()
+    for r in raw_streams:
+        F.fpca_stream_destroy(r)
     for hh in hs:
         hh.close()
     print(json.dumps(out), flush=True)

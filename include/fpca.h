@@ -86,6 +86,19 @@ int fpca_create(fpca_handle *handle, int device);
 int fpca_destroy(fpca_handle handle);
 /* stream: a hipStream_t of the handle's device, passed as void*. */
 int fpca_set_stream(fpca_handle handle, void *stream);
+/* A stream of device `device` whose kernels run only on the compute units
+ * selected by bits cu_begin .. cu_end-1 of the device's CU mask (the HIP
+ * runtime's mask for a stream; 0 <= cu_begin < cu_end <= the device's CU
+ * count). For running stages of a pipeline side by side on disjoint shares of
+ * the chip (for example one step's eigendecomposition beside the next step's
+ * binning and smoothing). The runtime spreads consecutive mask bits over the
+ * XCDs and refuses a mask that leaves one of them without a CU: on MI355X
+ * (256 CUs) the top 64 bits give 8 CUs on each XCD. Returns the stream in
+ * *stream (a hipStream_t, owned by the caller: fpca_stream_destroy);
+ * FPCA_ERR_INVALID_ARG for a bad device or range, FPCA_ERR_UNSUPPORTED when
+ * the runtime refuses the mask. */
+int fpca_stream_create_cu_range(int device, int cu_begin, int cu_end, void **stream);
+int fpca_stream_destroy(void *stream);
 /* Waits for the handle's stream; returns FPCA_ERR_DOMAIN (and clears the flag)
  * if a binning call met an observation outside [0,1]^d since the last sync. */
 int fpca_sync(fpca_handle handle);

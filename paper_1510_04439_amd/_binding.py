@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = [
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
     "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
     "fpca_set_conv", "fpca_covop_create", "fpca_covop_apply", "fpca_covop_destroy", "fpca_eig_covop",
-    "fpca_set_engine",
+    "fpca_set_engine", "fpca_stream_create_cu_range", "fpca_stream_destroy",
 ]
 
 
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     L.fpca_sync.argtypes = [vp]
     L.fpca_set_conv.argtypes = [vp, i32]
     L.fpca_set_engine.argtypes = [vp, i32]
+    L.fpca_stream_create_cu_range.argtypes = [i32, i32, i32, ctypes.POINTER(vp)]
+    L.fpca_stream_destroy.argtypes = [vp]
     L.fpca_covop_create.argtypes = [vp, ctypes.POINTER(_GridC), i64, vp, vp, ctypes.POINTER(ctypes.c_double), i32,
                                     ctypes.POINTER(vp)]
     L.fpca_covop_apply.argtypes = [vp, i32, vp, vp]
@@ -179,6 +181,18 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def fpca_stream_create_cu_range(device: int, cu_begin: int, cu_end: int) -> int:
+    """A stream on CU mask bits cu_begin..cu_end-1 of `device`; returns the hipStream_t as an int
+    (wrap it with torch.cuda.ExternalStream); release with fpca_stream_destroy."""
+    st = ctypes.c_void_p()
+    _check(load_library().fpca_stream_create_cu_range(int(device), int(cu_begin), int(cu_end), ctypes.byref(st)))
+    return int(st.value)
+
+
+def fpca_stream_destroy(stream: int):
+    _check(load_library().fpca_stream_destroy(ctypes.c_void_p(stream)))
 
 
 def fpca_bin(h: Handle, grid: Grid, kind: int, design: int, dtype: int, prec: int, n: int,

@@ -3,6 +3,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "common.hpp"
 
@@ -218,6 +219,38 @@ int fpca_destroy(fpca_handle ctx) {
 int fpca_set_stream(fpca_handle ctx, void *stream) {
   if (int rc = check_handle(ctx)) return rc;
   ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return FPCA_OK;
+}
+
+int fpca_stream_create_cu_range(int device, int cu_begin, int cu_end, void **stream) {
+  if (!stream) return set_error(FPCA_ERR_INVALID_ARG, "null stream pointer");
+  *stream = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return set_error(FPCA_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return set_error(FPCA_ERR_INVALID_ARG, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  FPCA_HIP(hipGetDeviceProperties(&prop, device));
+  const int n = prop.multiProcessorCount;
+  if (cu_begin < 0 || cu_end > n || cu_begin >= cu_end)
+    return set_error(FPCA_ERR_INVALID_ARG, "CU range [%d, %d) outside [0, %d)", cu_begin, cu_end, n);
+  std::vector<uint32_t> mask(size_t((n + 31) / 32), 0u);
+  for (int i = cu_begin; i < cu_end; ++i) mask[size_t(i / 32)] |= 1u << (i % 32);
+  int cur = 0;
+  FPCA_HIP(hipGetDevice(&cur));
+  FPCA_HIP(hipSetDevice(device));
+  hipStream_t st = nullptr;
+  const hipError_t e = hipExtStreamCreateWithCUMask(&st, uint32_t(mask.size()), mask.data());
+  (void)hipSetDevice(cur);
+  if (e != hipSuccess)
+    return set_error(FPCA_ERR_UNSUPPORTED, "the runtime refused CU range [%d, %d): %s", cu_begin, cu_end,
+                     hipGetErrorString(e));
+  *stream = st;
+  return FPCA_OK;
+}
+
+int fpca_stream_destroy(void *stream) {
+  if (!stream) return FPCA_OK;
+  FPCA_HIP(hipStreamDestroy(reinterpret_cast<hipStream_t>(stream)));
   return FPCA_OK;
 }
 
