@@ -358,12 +358,13 @@ int fpca_pace_scores(fpca_handle handle, const fpca_grid *grid, int design, int 
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): same arguments, same kernels and the same
  * results, but no allocation of any kind. The common-grid design's shared
- * k x k inverse and the partial sums it is formed from live in a fixed
- * per-GPU array of 106,752 bytes (k <= 32, the limit of fpca_pace_scores, so
- * every valid call fits), set up by fpca_create and held until the process
- * ends; the irregular design needs none. Every call on one GPU uses that GPU's array: calls that overlap in
- * time on one GPU (several streams or handles) race and must be serialized
- * by the caller. Errors as for fpca_pace_scores.
+ * k x k inverse, the partial sums it is formed from and two flags live in a
+ * fixed per-GPU array of 57,856 bytes (k <= 32, the limit of
+ * fpca_pace_scores, so every valid call fits), set up by fpca_create and held
+ * until the process ends; the irregular design needs none. Every call on one
+ * GPU uses that GPU's array: calls that overlap in time on one GPU (several
+ * streams or handles) race and must be serialized by the caller. Errors as
+ * for fpca_pace_scores.
  */
 int fpca_pace_scores_noalloc(fpca_handle handle, const fpca_grid *grid, int design, int dtype, int64_t n,
                              const int64_t *offsets, const void *t, const void *y, const void *mu,

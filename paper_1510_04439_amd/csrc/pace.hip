@@ -73,30 +73,19 @@ __device__ inline void load4(const double *p, double *o) {
   const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
   o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
 }
-constexpr int CG_THREADS = 1024;  // 16 wavefronts (the inverse)
-constexpr int CG_NG = 16;         // workgroups of the shared matrix's partial sums
-constexpr int CG_GT = 256;        // their threads (4 wavefronts)
 constexpr int MB = 8;             // MFMA steps (4 nodes each) whose operands are loaded together
 
-// Common grid: partial sums of Phi^T Phi over the P nodes, shared by every
-// curve observed at all of them. Workgroup b of CG_NG takes a contiguous
-// share of the nodes, each of its wavefronts a quarter of that, and
-// accumulates the 16 x 16 tiles (tr, tc) of Phi^T Phi with FP64 MFMA
-// (16 x 16 x 4: lane l carries Phi[16 tr + l % 16][node + l / 16] as the A
-// operand and the same for tc as the B operand), the operands of MB steps
-// loaded before they are used; the four wavefronts' tiles are summed in a
-// fixed order into part[b][tile] (tiles (0,0), (0,1), (1,1)).
+// Common grid: one wavefront's part of Phi^T Phi, the shared matrix of the
+// curves observed at every node: the 16 x 16 tiles (0,0), (0,1), (1,1) over
+// the nodes n0 .. n1-1 with FP64 MFMA (16 x 16 x 4: lane l carries
+// Phi[16 tr + l % 16][node + l / 16] as the A operand and the same for tc as
+// the B operand), the operands of MB steps loaded before they are used.
 template <typename T, bool VEC>
-__global__ __launch_bounds__(CG_GT) void k_pace_cg_gram(int64_t P, const T *__restrict__ efuns, int k,
-                                                        double *__restrict__ part) {
-  __shared__ double red[4][3][256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ inline void gram_wave(int64_t P, const T *__restrict__ efuns, int k, int64_t n0, int64_t n1, v4d &d00,
+                                 v4d &d01, v4d &d11) {
+  const int lane = threadIdx.x & 63;
   const int nt = k > 16 ? 2 : 1;
   const int row = lane & 15, kk = lane >> 4;
-  constexpr int NW = CG_NG * (CG_GT / 64);
-  const int64_t per = ((P + NW * 4 * MB - 1) / (NW * 4 * MB)) * 4 * MB;  // nodes per wavefront
-  const int64_t n0 = min(P, (int64_t(blockIdx.x) * (CG_GT / 64) + wave) * per), n1 = min(P, n0 + per);
-  v4d d00 = {0, 0, 0, 0}, d01 = d00, d11 = d00;
   const bool r0 = row < k, r1 = 16 + row < k;
   const T *f0p = efuns + int64_t(r0 ? row : 0) * P;
   const T *f1p = efuns + int64_t(r1 ? 16 + row : 0) * P;
@@ -137,45 +126,79 @@ __global__ __launch_bounds__(CG_GT) void k_pace_cg_gram(int64_t P, const T *__re
       }
     }
   }
+}
+
+// Words of the LDS pool of k_pace_cg_rhs: workgroup 0 holds A (k x k + 1
+// padding) and the two Gauss-Jordan buffers (k x 2k each), whose space first
+// holds four slots of the Gram tiles; the other workgroups hold their
+// wavefronts' tiles, the inverse and the right-hand sides.
+constexpr int CG_A = PACE_KMAX * (PACE_KMAX + 1);
+constexpr int CG_M = PACE_KMAX * 2 * PACE_KMAX;
+constexpr int CG_POOL = CG_A + 2 * CG_M;
+static_assert(4 * 3 * 256 <= 2 * CG_M, "the Gram slots fit in the Gauss-Jordan buffers");
+
+constexpr int CG_NGW = 8;  // workgroups of k_pace_cg_rhs that form partial sums of Phi^T Phi
+
+// Common grid: partial sums of Phi^T Phi (the shared matrix) over the share
+// b of CG_NGW of the nodes, by the NT threads of one workgroup: its
+// wavefronts take contiguous parts of that share (gram_wave), their tiles are
+// added in a fixed order (wavefronts 4g + w into LDS slot w, g = 0, 1, ...,
+// then the four slots) into part[b][tile].
+template <typename T, bool VEC, int NT>
+__device__ void cg_gram_part(int64_t P, const T *__restrict__ efuns, int k, int b, double *slot,
+                             double *__restrict__ part) {
+  constexpr int NW = NT / 64;
+  static_assert(NW % 4 == 0, "wavefronts come in fours");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = lane & 15, kk = lane >> 4;
+  constexpr int NWT = CG_NGW * NW;
+  const int64_t per = ((P + NWT * 4 * MB - 1) / (NWT * 4 * MB)) * 4 * MB;  // nodes per wavefront
+  const int64_t n0 = min(P, (int64_t(b) * NW + wave) * per), n1 = min(P, n0 + per);
+  v4d d00 = {0, 0, 0, 0}, d01 = d00, d11 = d00;
+  gram_wave<T, VEC>(P, efuns, k, n0, n1, d00, d01, d11);
   // D[i][j] of a tile sits in lane j + 16 (i % 4), element i / 4
+  for (int g = 0; g < NW / 4; ++g) {
+    if ((wave >> 2) == g) {
+      double *sw = slot + (wave & 3) * 3 * 256;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int e = (kk + 4 * v) * 16 + row;
-    red[wave][0][e] = d00[v];
-    red[wave][1][e] = d01[v];
-    red[wave][2][e] = d11[v];
+      for (int v = 0; v < 4; ++v) {
+        const int e = (kk + 4 * v) * 16 + row;
+        sw[e] = (g ? sw[e] : 0.0) + d00[v];
+        sw[256 + e] = (g ? sw[256 + e] : 0.0) + d01[v];
+        sw[512 + e] = (g ? sw[512 + e] : 0.0) + d11[v];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < 3 * 256; e += CG_GT) {
-    const int t = e / 256, ei = e % 256;
-    part[(int64_t(blockIdx.x) * 3 + t) * 256 + ei] = ((red[0][t][ei] + red[1][t][ei]) + red[2][t][ei]) + red[3][t][ei];
-  }
+  for (int e = tid; e < 3 * 256; e += NT)
+    part[int64_t(b) * 3 * 256 + e] = ((slot[e] + slot[768 + e]) + slot[1536 + e]) + slot[2304 + e];
 }
 
 // Common grid: the shared matrix Phi^T Phi + sigma^2 Lambda^{-1} from the
-// CG_NG partial sums (added in workgroup order) and its inverse (below), to
-// Lout. One workgroup.
-__global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg, const double *__restrict__ part,
-                                                             double *__restrict__ Lout, int *__restrict__ ok) {
-  __shared__ double M0b[PACE_KMAX][2 * PACE_KMAX];
-  __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
-  __shared__ double Mb[PACE_KMAX][2 * PACE_KMAX];
+// CG_NGW partial sums (added in workgroup order) and its inverse, to Lout, by
+// the NT threads of one workgroup.
+template <int NT>
+__device__ void cg_inverse(int k, const PaceDiag &dg, const double *__restrict__ part, double *pool,
+                           double *__restrict__ Lout, int *__restrict__ ok) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < k * k; e += CG_THREADS) {
+  double *A = pool;                    // [PACE_KMAX][PACE_KMAX + 1]
+  double *M0 = pool + CG_A;            // [PACE_KMAX][2 PACE_KMAX]
+  double *M1 = M0 + CG_M;
+  for (int e = tid; e < k * k; e += NT) {
     const int r = e / k, c = e % k;
     // the upper tiles only: entry (r, c) of tile (1, 0) is (c, r) of tile (0, 1)
     const int rr = (r >> 4) > (c >> 4) ? c : r, cc = (r >> 4) > (c >> 4) ? r : c;
     const int tr = rr >> 4, tc = cc >> 4;
     const int t = tr == 0 ? (tc == 0 ? 0 : 1) : 2;
     const int ei = (rr & 15) * 16 + (cc & 15);
-    double v[CG_NG];
+    double v[CG_NGW];
 #pragma unroll
-    for (int b = 0; b < CG_NG; ++b) v[b] = part[(int64_t(b) * 3 + t) * 256 + ei];
+    for (int b = 0; b < CG_NGW; ++b) v[b] = part[(int64_t(b) * 3 + t) * 256 + ei];
     double sum = 0.0;
 #pragma unroll
-    for (int b = 0; b < CG_NG; ++b) sum += v[b];
+    for (int b = 0; b < CG_NGW; ++b) sum += v[b];
     const bool kr = dg.v[r] >= 0.0, kc = dg.v[c] >= 0.0;
-    A[r][c] = (kr && kc) ? sum + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
+    A[r * (PACE_KMAX + 1) + c] = (kr && kc) ? sum + (r == c ? dg.v[r] : 0.0) : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
   // A^{-1} by Gauss-Jordan elimination on [A | I] (k x 2k), two LDS buffers
@@ -183,11 +206,10 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg,
   // symmetric positive definite when every kept component has lambda > 0;
   // the pivots are those of its LDL^T factorization, so a pivot <= 0 means it
   // is not: ok[0] = 0 (every curve then takes its own factorization).
-  double *M0 = &M0b[0][0], *M1 = &Mb[0][0];  // [PACE_KMAX][2 PACE_KMAX]
   constexpr int LDM = 2 * PACE_KMAX;
-  for (int e = tid; e < k * 2 * k; e += CG_THREADS) {
+  for (int e = tid; e < k * 2 * k; e += NT) {
     const int r = e / (2 * k), j = e % (2 * k);
-    M0[r * LDM + j] = j < k ? A[r][j] : (j - k == r ? 1.0 : 0.0);
+    M0[r * LDM + j] = j < k ? A[r * (PACE_KMAX + 1) + j] : (j - k == r ? 1.0 : 0.0);
   }
   __syncthreads();
   bool good = true;
@@ -197,7 +219,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg,
     const double piv = Mo[c * LDM + c];
     good = good && piv > 0.0;
     const double inv = 1.0 / piv;
-    for (int e = tid; e < k * 2 * k; e += CG_THREADS) {
+    for (int e = tid; e < k * 2 * k; e += NT) {
       const int r = e / (2 * k), j = e % (2 * k);
       const double pj = Mo[c * LDM + j] * inv;
       Mn[r * LDM + j] = r == c ? pj : fma(-Mo[r * LDM + c], pj, Mo[r * LDM + j]);
@@ -205,7 +227,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg,
     __syncthreads();
   }
   const double *Mf = (k & 1) ? M1 : M0;
-  for (int e = tid; e < k * k; e += CG_THREADS) Lout[e] = Mf[(e / k) * LDM + k + e % k];
+  for (int e = tid; e < k * k; e += NT) Lout[e] = Mf[(e / k) * LDM + k + e % k];
   if (tid == 0) ok[0] = good ? 1 : 0;
 }
 
@@ -218,25 +240,74 @@ __global__ __launch_bounds__(CG_THREADS) void k_pace_cg_prep(int k, PaceDiag dg,
 // before they are used; the wavefronts' tiles are summed in a fixed order. A
 // curve with a missing value
 // gets a NaN first score: k_pace solves it on its own. The scores are the
-// shared inverse times the right-hand sides.
+// shared inverse times the right-hand sides. Workgroups 1..CG_NGW form
+// partial sums of the shared matrix (cg_gram_part) and count themselves on
+// ready[1]; workgroup 0 adds them, inverts the matrix (cg_inverse) and
+// publishes the inverse through ready[0] (both cleared by k_pace_clear before
+// the launch), while the others form their right-hand sides. A workgroup that
+// finds a flag unset after its spin limit gives up the shared factor: its
+// curves go to k_pace.
 constexpr int RH_CURVES = 16;
+
+// Clears the flag through which k_pace_cg_rhs publishes the shared inverse
+// and the count of its partial sums (a kernel rather than a memset, so that
+// the call can be captured in a graph).
+__global__ void k_pace_clear(int *__restrict__ ready) {
+  if (threadIdx.x < 2) ready[threadIdx.x] = 0;
+}
 
 constexpr int RH_THREADS = 512;  // 8 wavefronts
 
 template <typename T, bool VEC>
 __global__ __launch_bounds__(RH_THREADS) void k_pace_cg_rhs(int64_t n, int64_t P, const T *__restrict__ y,
                                                       const T *__restrict__ mu, const T *__restrict__ efuns, int k,
-                                                      PaceDiag dg, const double *__restrict__ Lcg,
-                                                      const int *__restrict__ cg_ok, T *__restrict__ scores) {
-  __shared__ double red[4][2][256];
-  __shared__ double Ai[PACE_KMAX][PACE_KMAX + 1];
-  __shared__ double rhs[RH_CURVES][PACE_KMAX + 1];
+                                                      PaceDiag dg, double *__restrict__ gpart,
+                                                      double *__restrict__ Lcg, int *__restrict__ cg_ok,
+                                                      int *__restrict__ ready, T *__restrict__ scores) {
+  static_assert(4 * 2 * 256 + RH_CURVES * (PACE_KMAX + 1) + CG_A <= CG_POOL, "the right-hand sides fit the pool");
+  __shared__ double pool[CG_POOL];
+  auto red = reinterpret_cast<double(*)[2][256]>(pool);                             // [4][2][256]
+  auto Ai = reinterpret_cast<double(*)[PACE_KMAX + 1]>(pool + 4 * 2 * 256);        // [PACE_KMAX][..]
+  auto rhs = reinterpret_cast<double(*)[PACE_KMAX + 1]>(pool + 4 * 2 * 256 + CG_A);  // [RH_CURVES][..]
   constexpr int NW = RH_THREADS / 64;
   __shared__ int miss[RH_CURVES];
+  __shared__ int s_ok;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t c0 = int64_t(blockIdx.x) * RH_CURVES;
-  if (cg_ok[0] != 1) return;  // no shared factor: k_pace does every curve
-  for (int e = tid; e < k * k; e += RH_THREADS) Ai[e / k][e % k] = Lcg[e];
+  if (blockIdx.x == 0) {
+    // the partial sums of the CG_NGW workgroups that follow (counted on ready[1])
+    if (tid == 0) {
+      long long it = 0;
+      bool got = true;
+      while (__hip_atomic_load(ready + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < CG_NGW) {
+        if (++it > (1LL << 20)) {
+          got = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (got) got = __hip_atomic_load(ready + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == CG_NGW;
+      s_ok = got ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_ok) {
+      cg_inverse<RH_THREADS>(k, dg, gpart, pool, Lcg, cg_ok);
+    } else if (tid == 0) {
+      cg_ok[0] = 0;  // no shared factor: k_pace solves every curve
+    }
+    // every lane's stores are released before the flag is set
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  if (blockIdx.x <= CG_NGW) {
+    cg_gram_part<T, VEC, RH_THREADS>(P, efuns, k, blockIdx.x - 1, pool, gpart);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(ready + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  const int64_t c0 = int64_t(blockIdx.x - 1 - CG_NGW) * RH_CURVES;
   if (tid < RH_CURVES) miss[tid] = 0;
   __syncthreads();
   const int nt = k > 16 ? 2 : 1;
@@ -317,6 +388,29 @@ __global__ __launch_bounds__(RH_THREADS) void k_pace_cg_rhs(int64_t n, int64_t P
     for (int w = 0; w < 4; ++w) sum += red[w][tc][ei];
     rhs[ci][l] = dg.v[l] >= 0.0 ? sum : 0.0;
   }
+  // the shared inverse from workgroup 0 (long done by now, as a rule)
+  if (tid == 0) {
+    // spin on relaxed loads, then one acquiring load (one cache invalidation
+    // for the workgroup; the barrier below orders the other waves' loads)
+    long long it = 0;
+    bool got = true;
+    while (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      if (++it > (1LL << 20)) {
+        got = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (got) got = __hip_atomic_load(ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 1;
+    s_ok = (got && cg_ok[0] == 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_ok == 0) {
+    // no shared factor (or it never came): k_pace solves these curves
+    if (tid < RH_CURVES && c0 + tid < n) scores[(c0 + tid) * k] = T(__builtin_nan(""));
+    return;
+  }
+  for (int e = tid; e < k * k; e += RH_THREADS) Ai[e / k][e % k] = Lcg[e];
   __syncthreads();
   // scores = A^{-1} rhs, one thread per (curve, component)
   if (tid < RH_CURVES * k) {
@@ -471,10 +565,11 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
   }
 }
 
-// Scratch of the common-grid design: the shared k x k inverse, its flag and
-// the partial sums of Phi^T Phi (8,192 + 256 + 98,304 bytes).
-constexpr size_t PACE_PART_BYTES = size_t(CG_NG) * 3 * 256 * sizeof(double);
-constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256 + PACE_PART_BYTES;
+// Scratch of the common-grid design: the shared k x k inverse, its
+// positive-definiteness flag, the two flags of k_pace_cg_rhs and the partial
+// sums of Phi^T Phi (8,192 + 256 + 256 + 49,152 bytes).
+constexpr size_t PACE_PART_BYTES = size_t(CG_NGW) * 3 * 256 * sizeof(double);
+constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256 + 256 + PACE_PART_BYTES;
 
 // `fixed`: caller-provided scratch of PACE_SCRATCH_BYTES (the allocation-free
 // entry point), or NULL to carve it from the handle's arena.
@@ -491,26 +586,24 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
     Carver cv{static_cast<char *>(fixed ? fixed : ctx->ws), 0, fixed ? PACE_SCRATCH_BYTES : ctx->ws_size};
     double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
     int *okf = cv.take<int>(1);
+    int *ready = cv.take<int>(2);
     double *gpart = cv.take<double>(PACE_PART_BYTES / sizeof(double));
     // vector loads when every row starts on a 16-byte boundary
     const bool vec = g.P % 4 == 0 && (reinterpret_cast<uintptr_t>(efuns) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
-    if (vec)
-      hipLaunchKernelGGL((k_pace_cg_gram<T, true>), dim3(CG_NG), dim3(CG_GT), 0, ctx->stream, g.P, efuns, k, gpart);
-    else
-      hipLaunchKernelGGL((k_pace_cg_gram<T, false>), dim3(CG_NG), dim3(CG_GT), 0, ctx->stream, g.P, efuns, k, gpart);
-    FPCA_LAUNCH_CHECK("pace_cg_gram");
-    hipLaunchKernelGGL(k_pace_cg_prep, dim3(1), dim3(CG_THREADS), 0, ctx->stream, k, dg, gpart, L, okf);
-    FPCA_LAUNCH_CHECK("pace_cg_prep");
+    hipLaunchKernelGGL(k_pace_clear, dim3(1), dim3(64), 0, ctx->stream, ready);
+    FPCA_LAUNCH_CHECK("pace_clear");
     Lcg = L;
     cg_ok = okf;
-    const dim3 rgrid(unsigned((n + RH_CURVES - 1) / RH_CURVES));
+    // workgroup 0 inverts the shared matrix, the next CG_NGW form its partial
+    // sums, the others take 16 curves each
+    const dim3 rgrid(unsigned((n + RH_CURVES - 1) / RH_CURVES + 1 + CG_NGW));
     if (vec)
       hipLaunchKernelGGL((k_pace_cg_rhs<T, true>), rgrid, dim3(RH_THREADS), 0, ctx->stream, n, g.P, y, mu, efuns, k,
-                         dg, Lcg, cg_ok, scores);
+                         dg, gpart, L, okf, ready, scores);
     else
       hipLaunchKernelGGL((k_pace_cg_rhs<T, false>), rgrid, dim3(RH_THREADS), 0, ctx->stream, n, g.P, y, mu, efuns, k,
-                         dg, Lcg, cg_ok, scores);
+                         dg, gpart, L, okf, ready, scores);
     FPCA_LAUNCH_CHECK("pace_cg_rhs");
   }
   // grid-stride over the curves; on the common grid most of them are done
