@@ -232,6 +232,11 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
   // response moments of the near-diagonal nodes, per wavefront: rows
   // t1-2R .. t1, lanes t2-2R .. t2+2R
   __shared__ float nearT[TW][2 * R + 1][4 * R + 1][5];
+  // The row loop's transposed writes (Gamma(p, t) for the TW columns t of the
+  // workgroup) gathered per output row, so that wavefront 0 writes each p's
+  // TW consecutive values at once, one row later; status -1: not emitted.
+  __shared__ float tq_v[2][64][TW];
+  __shared__ int8_t tq_s[2][64][TW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Chunk order: the chunks sharing a 128-byte line of a row (CPL chunks of
   // TW floats) land on one XCD (dispatch is round-robin over 8 XCDs), and the
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
 #pragma unroll
     for (int i = 0; i < W; ++i) win[a][i] = 0.f;
   for (int e = tid; e < 2 * NU * SW * (TW + 1); e += ST) (&stage[0][0][0][0])[e] = 0.f;
+  for (int e = tid; e < 2 * 64 * TW; e += ST) (&tq_s[0][0][0])[e] = -1;
 
   // Each thread stages NU values per row (64 s2 x TW t per array);
   // the next row is fetched into registers while the current one is used.
@@ -322,15 +328,53 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
       pre[a] = (r < M1 && lok) ? U[a * PP + (int64_t(r) * M2 + ls2) * P + t0 + ltt] : 0.f;
   };
   // Gamma(p,t) = Gamma(t,p) = b0 - mu_p mu_t (0 outside the domain), status at both.
-  auto emit = [&](int64_t p, double b0, int8_t st) {
+  // eb >= 0: the transposed write goes through tq_v / tq_s[eb] (row loop)
+  auto emit = [&](int64_t p, double b0, int8_t st, int eb) {
     if (mu) b0 -= double(mu[p]) * double(mu[t]);
     if (mask && (!mask[p] || !mask[t])) b0 = 0.0;
     const float v = float(b0);
     gamma[t * P + p] = v;
-    gamma[p * P + t] = v;
-    if (status) {
-      status[t * P + p] = st;
-      status[p * P + t] = st;
+    if (status) status[t * P + p] = st;
+    if (eb >= 0) {
+      tq_v[eb][lane][wave] = v;
+      tq_s[eb][lane][wave] = st;
+    } else {
+      gamma[p * P + t] = v;
+      if (status) status[p * P + t] = st;
+    }
+  };
+  // wavefront 0: the gathered transposed writes of output row x (buffer eb)
+  const bool vec4 = P % TW == 0 && (reinterpret_cast<uintptr_t>(gamma) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(status) & 3) == 0;
+  auto flush = [&](int eb, int x) {
+    if (x < 0 || lane >= M2) return;
+    const int64_t p = int64_t(x) * M2 + lane;
+    float v[TW];
+    int8_t sv[TW];
+    bool all = true, any = false;
+#pragma unroll
+    for (int w = 0; w < TW; ++w) {
+      v[w] = tq_v[eb][lane][w];
+      sv[w] = tq_s[eb][lane][w];
+      all = all && sv[w] >= 0;
+      any = any || sv[w] >= 0;
+    }
+    if (!any) return;
+    float *g = gamma + p * P + t0;
+    int8_t *sp = status ? status + p * P + t0 : nullptr;
+    if (all && vec4) {
+      static_assert(TW == 4, "one 16-byte and one 4-byte store per p");
+      *reinterpret_cast<float4 *>(g) = make_float4(v[0], v[1], v[2], v[3]);
+      if (sp)
+        *reinterpret_cast<uint32_t *>(sp) = uint32_t(uint8_t(sv[0])) | (uint32_t(uint8_t(sv[1])) << 8) |
+                                            (uint32_t(uint8_t(sv[2])) << 16) | (uint32_t(uint8_t(sv[3])) << 24);
+    } else {
+#pragma unroll
+      for (int w = 0; w < TW; ++w)
+        if (sv[w] >= 0) {
+          g[w] = v[w];
+          if (sp) sp[w] = sv[w];
+        }
     }
   };
   const int rlast = xmax + R;  // last input row any wavefront needs
@@ -342,6 +386,9 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
     for (int a = 0; a < NU; ++a) stage[buf][a][R + ls2][ltt] = pre[a];
     __syncthreads();
     if (r < rlast) fetch(r + 1);
+    // the previous row's transposed writes; this row's slots start empty
+    if (wave == 0) flush(buf ^ 1, r - 1 - R);
+    tq_s[buf][lane][wave] = -1;
     // s2 pass of input row r (lanes = s2) from the staged row
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
@@ -400,11 +447,13 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
     if (tz_ok && xc[3] != 0.0) {
       emit(p, (m[15] * (1.0 + tz_c + xc[2]) - xc[1] * m[16] - tz_a[0] * m[17] - tz_a[1] * m[18] -
                tz_a[2] * m[19]) * inv,
-           FPCA_STATUS_OK);
+           FPCA_STATUS_OK, buf);
     } else {
-      emit(p, m[15] * inv, FPCA_STATUS_FALLBACK);
+      emit(p, m[15] * inv, FPCA_STATUS_FALLBACK, buf);
     }
   }
+  __syncthreads();
+  if (wave == 0) flush(rlast & 1, rlast - R);
 
   // Nodes whose s- and t-windows share grid nodes (|s1 - t1| <= 2R and
   // |s2 - t2| <= 2R): the diagonal exclusion couples s and t, full system.
@@ -435,7 +484,7 @@ __global__ __launch_bounds__(ST) void k_stage_s(int M1, int M2, int64_t P, const
     for (int k = 0; k < 5; ++k) m[15 + k] = nq[k];
     int8_t st;
     const double b0 = wls_b0<4>(m, &st);
-    emit(p, b0, st);
+    emit(p, b0, st, -1);
   }
 }
 
