@@ -1,7 +1,8 @@
 // Linear binning (Section 3.2) of observations for the mean (eq. 2.3) and the
 // raw covariance (eq. 2.4).
 //
-// Mean: each observation scatters its 2^d multilinear weights with atomics.
+// Mean: each observation scatters its 2^d multilinear weights with atomics
+// (into per-workgroup LDS sums on small grids, added without atomics after).
 // Covariance, irregular design: the ordered-pair sums are assembled by the
 // Gram identity
 //   G = sum_i w_i (z_i z_i^T - sum_j Y_ij^2 b_ij b_ij^T),  z_i = sum_j b_ij Y_ij,
@@ -56,6 +57,99 @@ __global__ __launch_bounds__(256) void k_bin_mean(GridDims g, int64_t n, const i
       if (idx) idx[j] = int32_t(lower);
       if (cnt) atomicAdd(&cnt[lower], 1ull);
     }
+  }
+}
+
+// Mean binning on small grids (MB_PMAX nodes or fewer): the same scatter into
+// FP64 accumulators in LDS (one set per workgroup, grid-stride over the
+// curves), then each workgroup writes its sums to part[blockIdx][a][p]; the
+// finish kernel adds the workgroups' sums in workgroup order. On a small
+// grid every observation lands on a few hundred nodes, where global atomics
+// from all workgroups queue on the same addresses.
+constexpr int MB_PMAX = 2048;
+constexpr int MB_WGS = 256;  // workgroups of the scatter
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_mean_lds(GridDims g, int64_t n, const int64_t *__restrict__ off,
+                                                       const T *__restrict__ t, const T *__restrict__ y, int narr,
+                                                       double *__restrict__ part, int32_t *idx,
+                                                       unsigned long long *cnt, int *flags) {
+  __shared__ double acc[3][MB_PMAX];
+  const int P = int(g.P);
+  for (int e = threadIdx.x; e < narr * P; e += blockDim.x) acc[e / P][e % P] = 0.0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t a = off[i], b = off[i + 1];
+    if (b <= a) continue;
+    const double w = 1.0 / double(b - a);
+    for (int64_t j = a + threadIdx.x; j < b; j += blockDim.x) {
+      int k[3];
+      double rho[3];
+      if (!locate(t + j * g.d, g, k, rho)) {
+        atomicOr(flags, 1);
+        if (idx) idx[j] = -1;
+        continue;
+      }
+      const double yv = double(y[j]);
+      int64_t lower = 0;
+      for (int q = 0; q < g.d; ++q) lower += int64_t(k[q]) * g.stride[q];
+      for (int cc = 0; cc < (1 << g.d); ++cc) {
+        int64_t p;
+        double W;
+        corner(g, k, rho, cc, &p, &W);
+        const double ww = w * W;
+        atomicAdd(&acc[0][p], ww);
+        atomicAdd(&acc[1][p], ww * yv);
+        if (narr > 2) atomicAdd(&acc[2][p], ww * yv * yv);
+      }
+      if (idx) idx[j] = int32_t(lower);
+      if (cnt) atomicAdd(&cnt[lower], 1ull);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < narr * P; e += blockDim.x)
+    part[int64_t(blockIdx.x) * narr * P + e] = acc[e / P][e % P];
+}
+
+// Sum over the nwg workgroups' partials of element e: 16 lanes per element,
+// lane g adds partials g, g + 16, ... (up to 16 loads in flight), then the 16
+// lane sums are combined pairwise in a fixed order.
+constexpr int WS_LANES = 16;
+template <typename PT>
+__device__ inline double sum_over_wgs(const PT *__restrict__ part, int64_t stride, int nwg, int64_t e, bool in,
+                                      double (*red)[256 / WS_LANES]) {
+  const int g = threadIdx.x / (256 / WS_LANES), el = threadIdx.x % (256 / WS_LANES);
+  double sacc = 0.0;
+  for (int w0 = g; w0 < nwg; w0 += WS_LANES * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int w = w0 + WS_LANES * u;
+      v[u] = (in && w < nwg) ? double(part[int64_t(w) * stride + e]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sacc += v[u];
+  }
+  red[g][el] = sacc;
+  __syncthreads();
+#pragma unroll
+  for (int wd = WS_LANES / 2; wd > 0; wd >>= 1) {
+    if (g < wd) red[g][el] += red[g + wd][el];
+    __syncthreads();
+  }
+  return red[0][el];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_mean_finish(int64_t P, int narr, int nwg,
+                                                          const double *__restrict__ part, T *c, T *s, T *s2) {
+  __shared__ double red[WS_LANES][256 / WS_LANES];
+  const int64_t e = int64_t(blockIdx.x) * (256 / WS_LANES) + threadIdx.x % (256 / WS_LANES);
+  const bool in = e < narr * P;
+  const double sum = sum_over_wgs(part, int64_t(narr) * P, nwg, e, in, red);
+  if (in && threadIdx.x < 256 / WS_LANES) {
+    const int a = int(e / P);
+    const int64_t p = e % P;
+    (a == 0 ? c : (a == 1 ? s : s2))[p] = T(sum);
   }
 }
 
@@ -281,6 +375,104 @@ __global__ __launch_bounds__(256) void k_pair_diag(GridDims g, int64_t n, const 
   }
 }
 
+// The same j = l terms on small grids without folds: every such pair (u, v)
+// joins two corners of one cell, so it is node u and one of the 3^d
+// neighbours u + sum_q dq stride_q (dq in {-1, 0, 1}). Each workgroup
+// (grid-stride over the curves) adds the terms into FP32 sums per (node,
+// neighbour) in LDS (in the storage type T: FP32 sums for FP32 data, FP64
+// for FP64) and writes them to part[blockIdx][a][node][neighbour];
+// k_pair_diag_finish adds the workgroups' sums in workgroup order (FP64) and
+// subtracts them from C, G and Q.
+constexpr size_t PD_LDS_MAX = 128 * 1024;  // bytes of LDS for the sums
+constexpr int PD_WGS = 256;                // workgroups of the scatter
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_diag_lds(GridDims g, int64_t n, const int64_t *__restrict__ off,
+                                                        const T *__restrict__ t, const T *__restrict__ y, int narr,
+                                                        T *__restrict__ part, unsigned long long *cnt) {
+  extern __shared__ __align__(8) unsigned char pacc_raw[];
+  T *pacc = reinterpret_cast<T *>(pacc_raw);  // [narr][P][nb]
+  const int P = int(g.P);
+  int nb = 1;
+  for (int q = 0; q < g.d; ++q) nb *= 3;
+  const int tot = narr * P * nb;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) pacc[e] = T(0);
+  __syncthreads();
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t a = off[i], b = off[i + 1];
+    const int64_t Ni = b - a;
+    if (Ni < 2) continue;
+    const double w = 1.0 / (double(Ni) * double(Ni - 1));
+    for (int64_t j = a + threadIdx.x; j < b; j += blockDim.x) {
+      int k[3];
+      double rho[3];
+      if (!locate(t + j * g.d, g, k, rho)) continue;
+      const double yv = double(y[j]);
+      const double y2 = yv * yv;
+      const int nc = 1 << g.d;
+      int64_t pu[8];
+      double Wu[8];
+      for (int cc = 0; cc < nc; ++cc) corner(g, k, rho, cc, &pu[cc], &Wu[cc]);
+      for (int u = 0; u < nc; ++u)
+        for (int v = 0; v < nc; ++v) {
+          const double ww = w * Wu[u] * Wu[v];
+          if (ww == 0.0) continue;
+          // digit q of bi: the step of coordinate q from corner u to corner v
+          // (corner() takes coordinate q from bit d-1-q of the corner index)
+          int bi = 0, m = 1;
+          for (int q = 0; q < g.d; ++q, m *= 3) {
+            const int sh = g.d - 1 - q;
+            bi += (((v >> sh) & 1) - ((u >> sh) & 1) + 1) * m;
+          }
+          T *ac = pacc + int64_t(pu[u]) * nb + bi;
+          atomicAdd(ac, T(ww));
+          atomicAdd(ac + int64_t(P) * nb, T(ww * y2));
+          if (narr > 2) atomicAdd(ac + 2 * int64_t(P) * nb, T(ww * y2 * y2));
+        }
+      if (cnt) {
+        int64_t lower = 0;
+        for (int q = 0; q < g.d; ++q) lower += int64_t(k[q]) * g.stride[q];
+        atomicAdd(&cnt[lower * g.P + lower], (unsigned long long)(-1ll));
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) part[int64_t(blockIdx.x) * tot + e] = pacc[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_diag_finish(GridDims g, int narr, int nwg,
+                                                           const T *__restrict__ part, T *C, T *G, T *Q) {
+  __shared__ double red[WS_LANES][256 / WS_LANES];
+  const int P = int(g.P);
+  int nb = 1;
+  for (int q = 0; q < g.d; ++q) nb *= 3;
+  // element (node, neighbour) of this lane group
+  const int64_t e = int64_t(blockIdx.x) * (256 / WS_LANES) + threadIdx.x % (256 / WS_LANES);
+  const bool in = e < int64_t(P) * nb;
+  const int p = in ? int(e / nb) : 0, bi = in ? int(e % nb) : 0;
+  // the neighbour's node, if it exists
+  int64_t qn = p;
+  int m = bi;
+  bool ok = in;
+  for (int q = 0; q < g.d; ++q) {
+    const int dq = m % 3 - 1;
+    m /= 3;
+    const int kq = int((p / g.stride[q]) % g.M[q]);
+    if (kq + dq < 0 || kq + dq >= g.M[q]) ok = false;
+    qn += int64_t(dq) * g.stride[q];
+  }
+  const int64_t tot = int64_t(narr) * P * nb;
+  for (int a = 0; a < narr; ++a) {
+    const double sum = sum_over_wgs(part + int64_t(a) * P * nb, tot, nwg, e, ok, red);
+    if (ok && threadIdx.x < 256 / WS_LANES && sum != 0.0) {
+      T *A = a == 0 ? C : (a == 1 ? G : Q);
+      const int64_t o = int64_t(p) * P + qn;
+      A[o] = T(double(A[o]) - sum);
+    }
+    __syncthreads();  // red is reused for the next array
+  }
+}
+
 // Slab 0 = sum of the fold slabs.
 template <typename T>
 __global__ void k_sum_slabs(T *A, int64_t slab, int nf) {
@@ -328,13 +520,29 @@ int bin_impl(fpca_context *ctx, const fpca_grid *grid, int kind, int design, int
   const int64_t P = g.P;
   if (kind == FPCA_BIN_MEAN) {
     if (design == FPCA_IRREGULAR) {
-      if (int rc = fill_bytes_zero(ctx, W, P * sizeof(T))) return rc;
-      if (int rc = fill_bytes_zero(ctx, S, P * sizeof(T))) return rc;
-      if (SQ)
-        if (int rc = fill_bytes_zero(ctx, SQ, P * sizeof(T))) return rc;
+      const bool lds = P <= MB_PMAX && n > 0;  // the finish kernel writes every node
+      if (!lds) {
+        if (int rc = fill_bytes_zero(ctx, W, P * sizeof(T))) return rc;
+        if (int rc = fill_bytes_zero(ctx, S, P * sizeof(T))) return rc;
+        if (SQ)
+          if (int rc = fill_bytes_zero(ctx, SQ, P * sizeof(T))) return rc;
+      }
       if (cell_count)
         if (int rc = fill_i64(ctx, cell_count, 0, P)) return rc;
       if (n == 0) return FPCA_OK;
+      if (lds) {
+        const int narr = SQ ? 3 : 2;
+        const int nwg = int(n < MB_WGS ? n : MB_WGS);
+        if (int rc = ws_reserve(ctx, carve_bytes(size_t(nwg) * narr * P, 8))) return rc;
+        double *part = static_cast<double *>(ctx->ws);
+        hipLaunchKernelGGL(k_bin_mean_lds<T>, dim3(unsigned(nwg)), dim3(256), 0, ctx->stream, g, n, offsets, t, y,
+                           narr, part, bin_index, reinterpret_cast<unsigned long long *>(cell_count), ctx->d_flags);
+        FPCA_LAUNCH_CHECK("bin_mean_lds");
+        hipLaunchKernelGGL(k_bin_mean_finish<T>, dim3(unsigned((narr * P + 15) / 16)), dim3(256), 0, ctx->stream, P,
+                           narr, nwg, part, W, S, SQ);
+        FPCA_LAUNCH_CHECK("bin_mean_finish");
+        return FPCA_OK;
+      }
       unsigned blocks = unsigned(n < 16384 ? n : 16384);
       hipLaunchKernelGGL(k_bin_mean<T>, dim3(blocks), dim3(256), 0, ctx->stream, g, n, offsets, t, y, W, S, SQ,
                          bin_index, reinterpret_cast<unsigned long long *>(cell_count), ctx->d_flags);
@@ -457,6 +665,28 @@ int bin_impl(fpca_context *ctx, const fpca_grid *grid, int kind, int design, int
     if (int rc = gram_i32(ctx, cntrow, n, P, cell_count)) return rc;
   }
   if (n > 0) {
+    int nb = 1;
+    for (int q = 0; q < g.d; ++q) nb *= 3;
+    const int narr = SQ ? 3 : 2;
+    const size_t lds = size_t(narr) * size_t(P) * nb * sizeof(T);
+    if (nsl == 1 && lds <= PD_LDS_MAX) {
+      static size_t lds_set = 0;  // the attribute is set once per size (not inside a captured stream)
+      if (lds > lds_set) {
+        FPCA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pair_diag_lds<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(PD_LDS_MAX)));
+        lds_set = PD_LDS_MAX;
+      }
+      const int nwg = int(n < PD_WGS ? n : PD_WGS);
+      if (int rc = ws_reserve(ctx, carve_bytes(size_t(nwg) * narr * P * nb, sizeof(T)))) return rc;
+      T *part = static_cast<T *>(ctx->ws);
+      hipLaunchKernelGGL(k_pair_diag_lds<T>, dim3(unsigned(nwg)), dim3(256), lds, ctx->stream, g, n, offsets, t, y,
+                         narr, part, reinterpret_cast<unsigned long long *>(cell_count));
+      FPCA_LAUNCH_CHECK("pair_diag_lds");
+      hipLaunchKernelGGL(k_pair_diag_finish<T>, dim3(unsigned((int64_t(P) * nb + 15) / 16)), dim3(256), 0,
+                         ctx->stream, g, narr, nwg, part, W, S, SQ);
+      FPCA_LAUNCH_CHECK("pair_diag_finish");
+      return FPCA_OK;
+    }
     hipLaunchKernelGGL(k_pair_diag<T>, dim3(blocks), dim3(256), 0, ctx->stream, g, n, offsets, t, y,
                        nsl > 1 ? fold : nullptr, n_folds, W, S, SQ, slab,
                        reinterpret_cast<unsigned long long *>(cell_count));

@@ -97,7 +97,8 @@ def test_bin_mean_parity(torch, F, h, d, M, dt):
 
 @pytest.mark.parametrize("d,M,dt,nf,bf", [(1, (21,), "f64", 0, False), (2, (9, 8), "f32", 3, False),
                                           (3, (5, 4, 6), "f32", 5, False), (2, (16, 16), "f32", 0, False),
-                                          (2, (9, 8), "f32", 3, True), (2, (12, 11), "f32", 0, True)])
+                                          (2, (9, 8), "f32", 3, True), (2, (12, 11), "f32", 0, True),
+                                          (3, (5, 4, 6), "f32", 0, False), (3, (4, 5, 3), "f64", 0, False)])
 def test_bin_cov_parity(torch, F, h, d, M, dt, nf, bf):
     """bf: the Gram product in BF16x3 (bf16 hi/lo split, three products, FP32
     accumulation); its stated bound is 1e-4 normwise."""
