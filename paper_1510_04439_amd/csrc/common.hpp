@@ -55,6 +55,16 @@ struct fpca_context {
 
 namespace fpca {
 
+// bf16 split of an FP32 value (the BF16x3 products): hi = round-to-nearest-even
+// bf16(x), lo = bf16(x - hi).
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
 int set_error(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 

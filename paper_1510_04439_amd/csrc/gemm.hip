@@ -56,14 +56,6 @@ __device__ inline bool tile_of(int id, int nb, int per, int *bi, int *bj) {
   return band_tile((id % XCDS) * per + id / XCDS, nb, bi, bj);
 }
 
-// bf16 split of an FP32 value: hi = round-to-nearest-even bf16(x), lo = bf16(x - hi).
-__device__ inline unsigned short bf16_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  unsigned int lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
 // FP32 operands on v_mfma_f32_16x16x4_f32.
 template <bool VEC4>
@@ -248,26 +240,33 @@ __device__ inline int64_t sk_end(const SkPlan &pl, int u) {
 }
 
 // C = alpha * A^T A from the split operands; tiles of 128x128 on or above the
-// diagonal (mirrored), 4 wavefronts of 64x64. K goes through LDS 64 at a time
-// (the next 64 wait in registers) as two MFMA k-steps of 32, the second
-// step's operands read while the first step's MFMAs run. Per 16x16 block and
-// k-step: lo*hi + hi*lo + hi*hi on
+// diagonal (mirrored), 4 wavefronts of 64x64. K goes through LDS 32 at a time
+// (one MFMA k-step) in two buffers: the operands of the next step are copied
+// from memory straight into the other buffer (16-byte LDS DMA, no registers)
+// while this step's MFMAs run, one barrier per step. An LDS row holds the 32 k
+// of one operand row as four 16-byte chunks, chunk c of row r at position
+// c ^ swz(r), so that the 16 rows an MFMA operand read touches fall on
+// distinct banks. Per 16x16 block and k-step: lo*hi + hi*lo + hi*hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the lo*lo term, below
 // 2^-16 of the product, is dropped). Whole tiles are written to C; a piece of
 // a split tile leaves its accumulators in its partial slot for k_syrk_fixup.
+// Rows past N are loaded from row N - 1: they only reach outputs past N,
+// which are not written.
+__device__ inline int syrk_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
 __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__restrict__ Th,
                                                          const unsigned short *__restrict__ Tl, int64_t Kp, int64_t N,
                                                          float *__restrict__ C, int64_t ldc, float alpha,
                                                          int zero_diag, int nb, SkPlan pl,
                                                          float *__restrict__ part, int vec4) {
-  constexpr int BK = 64;       // K per LDS fill: two MFMA k-steps of 32
-  constexpr int LR = BK + 8;   // padded LDS row in bf16 elements (144 bytes)
-  // one fill [Ah Al Bh Bl][row][k]; the next fill waits in registers
-  __shared__ __attribute__((aligned(16))) unsigned short S[4][TB][LR];
+  constexpr int BK = 32;  // K per LDS buffer: one MFMA k-step
+  constexpr int SBYTES = 2 * 4 * TB * BK * 2;        // [buf][Ah Al Bh Bl][row][k] in bf16
+  constexpr int TBYTES = TB * (TB + 1) * 4;          // the epilogue's float tile
+  __shared__ __attribute__((aligned(16))) unsigned char lds[SBYTES > TBYTES ? SBYTES : TBYTES];
+  auto S = reinterpret_cast<unsigned short(*)[4][TB][BK]>(lds);
   const int w = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int kq = (lane >> 4) * 8;
   const int u = sk_rank(pl, w);
   const int64_t j0 = sk_begin(pl, u), j1 = sk_end(pl, u);
   const int nwhole = pl.F;  // waves of whole tiles
@@ -300,53 +299,46 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) acc[i][jj] = float4_t{0.f, 0.f, 0.f, 0.f};
-    // staging: 128 rows x 8 chunks of 16 bytes per array; 4 chunks per thread
-    u16x8 st[4][4];
-    auto load = [&](int64_t kb) {
+    // one buffer: per array 128 rows x 4 chunks = 8 wave copies of 64 chunks;
+    // wavefront v takes copies v and v + 4 of every array. Lane L of copy cp
+    // fills position L % 4 of row 16 cp + L / 4, i.e. chunk (L % 4) ^ swz(row).
+    auto dma = [&](int64_t kb, int buf) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (a >= narr) break;
         const unsigned short *src = (a & 1) ? Tl : Th;
         const int64_t r0 = (a < 2) ? m0 : n0;
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const int c = tid + 256 * h;
-          const int row = c >> 3, pt = c & 7;
-          const int64_t gr = r0 + row;
-          if (gr < N)
-            st[a][h] = *reinterpret_cast<const u16x8 *>(src + gr * Kp + kb + pt * 8);
-          else
-            st[a][h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        }
-      }
-    };
-    auto store = [&]() {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if (a >= narr) break;
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const int c = tid + 256 * h;
-          *reinterpret_cast<u16x8 *>(&S[a][c >> 3][(c & 7) * 8]) = st[a][h];
+        for (int h = 0; h < 2; ++h) {
+          const int cp = wave + 4 * h;
+          const int row = 16 * cp + (lane >> 2);
+          const int ch = (lane & 3) ^ syrk_swz(row);
+          const int64_t gr = min(r0 + row, N - 1);
+          __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + gr * Kp + kb + ch * 8),
+                                           (__attribute__((address_space(3))) void *)(&S[buf][a][16 * cp][0]), 16,
+                                           0, 0);
         }
       }
     };
     const int bh = diag_tile ? 0 : 2, bl = diag_tile ? 1 : 3;
-    // operands of the k-step at offset ks of the fill
-    auto frag = [&](int ks, bf16x8 *ah, bf16x8 *al, bf16x8 *bhv, bf16x8 *blv) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = wm * 64 + i * 16 + (lane & 15);
-        ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[0][r][ks + kq]));
-        al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[1][r][ks + kq]));
-        const int c = wn * 64 + i * 16 + (lane & 15);
-        bhv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[bh][c][ks + kq]));
-        blv[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[bl][c][ks + kq]));
-      }
+    // lane l reads chunk l / 16 of rows l % 16 (+ 16 i) of its wavefront's 64
+    const int kc = lane >> 4;
+    auto rd = [&](int buf, int a, int r) {
+      return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&S[buf][a][r][8 * (kc ^ syrk_swz(r))]));
     };
     // the three products of a block are 16 MFMAs apart (independent
     // accumulators in between), so no MFMA waits on its predecessor
-    auto mma = [&](const bf16x8 *ah, const bf16x8 *al, const bf16x8 *bhv, const bf16x8 *blv) {
+    auto step = [&](int buf) {
+      bf16x8 ah[4], al[4], bhv[4], blv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm * 64 + i * 16 + (lane & 15);
+        const int c = wn * 64 + i * 16 + (lane & 15);
+        ah[i] = rd(buf, 0, r);
+        al[i] = rd(buf, 1, r);
+        bhv[i] = rd(buf, bh, c);
+        blv[i] = rd(buf, bl, c);
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -363,27 +355,27 @@ __global__ __launch_bounds__(256, 2) void k_syrk_bf16x3(const unsigned short *__
         for (int jj = 0; jj < 4; ++jj)
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bhv[jj], acc[i][jj], 0, 0, 0);
     };
-    const int64_t kb0 = int64_t(k0) * BK, kb1 = int64_t(k1) * BK;
-    load(kb0);
+    // the plan counts K in steps of 64: two LDS buffers' worth each
+    const int64_t kb0 = int64_t(k0) * 64, kb1 = int64_t(k1) * 64;
+    dma(kb0, 0);
+    int buf = 0;
     for (int64_t kb = kb0; kb < kb1; kb += BK) {
-      store();
+      // this wavefront's copies have landed; after the barrier every
+      // wavefront's have, and every wavefront is done with the other buffer
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (kb + BK < kb1) load(kb + BK);
-      // the second k-step's operands are read while the first k-step's MFMAs run
-      bf16x8 a0h[4], a0l[4], b0h[4], b0l[4], a1h[4], a1l[4], b1h[4], b1l[4];
-      frag(0, a0h, a0l, b0h, b0l);
-      frag(32, a1h, a1l, b1h, b1l);
-      mma(a0h, a0l, b0h, b0l);
-      mma(a1h, a1l, b1h, b1l);
-      __syncthreads();  // the next fill overwrites S
+      if (kb + BK < kb1) dma(kb + BK, buf ^ 1);
+      step(buf);
+      buf ^= 1;
     }
+    __syncthreads();  // the epilogue and the next segment reuse the buffers
     // D layout of a 16x16 MFMA block: lane l, element e -> row 4*(l/16)+e, column l%16
     if (slot < 0) {
       // through LDS (free after the last step's barrier): rows of the tile and
       // rows of its mirror leave as whole 512-byte rows
       constexpr int LDT = TB + 1;
-      static_assert(sizeof(S) >= sizeof(float) * TB * LDT, "the epilogue tile fits in the staging buffers");
-      float *T = reinterpret_cast<float *>(&S[0][0][0]);
+      static_assert(TBYTES >= sizeof(float) * TB * LDT, "the epilogue tile fits in the LDS array");
+      float *T = reinterpret_cast<float *>(lds);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
