@@ -342,10 +342,14 @@ def main():
     ap.add_argument("--no-f2", action="store_true", help="skip the covariance-operator (64^3) timing")
     ap.add_argument("--no-fits", action="store_true", help="skip the d=1 and d=2 irregular end-to-end fits")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--eig-cus", type=int, default=0,
+                    help="CUs of the pipelined steps' eigendecomposition streams (0: a quarter of the chip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference for HBM byte counters)")
     ap.add_argument("--gram-prec", choices=["bf16x3", "f32"], default="bf16x3",
                     help="precision of the binning Gram product (bf16 hi/lo x3 with FP32 accumulation, or FP32)")
+    ap.add_argument("--panel-prec", choices=["bf16x3", "f32"], default="bf16x3",
+                    help="precision of the range finder's products of the covariance with the basis")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -385,7 +389,7 @@ def main():
     # unsplit; 32 or 96 CUs for it measured 1.25 and 0.97 ms). Plain streams
     # when the runtime refuses the masks.
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    eig_cus = max(32, (ncu // 4) // 32 * 32)
+    eig_cus = args.eig_cus if args.eig_cus > 0 else max(32, (ncu // 4) // 32 * 32)
     raw_streams = []
     try:
         for lo, hi in ((0, ncu - eig_cus), (0, ncu - eig_cus), (ncu - eig_cus, ncu), (ncu - eig_cus, ncu)):
@@ -401,6 +405,7 @@ def main():
         split = "one stream per step slot (CU masks refused)"
     step_done = [torch.cuda.Event(), torch.cuda.Event()]
     gram_prec = F.FPCA_PREC_BF16X3 if args.gram_prec == "bf16x3" else F.FPCA_PREC_F32
+    panel_prec = F.FPCA_PREC_BF16X3 if args.panel_prec == "bf16x3" else F.FPCA_PREC_F32
 
     def stages(slot, ev=None):
         """Binning and smoothing of one step on slot's handle, buffers and (current) stream;
@@ -422,7 +427,7 @@ def main():
 
     def eig(slot, ev=None):
         hh, b = hs[slot], bl[slot]
-        b.evals, b.fve = F.fpca_eig_randomized(hh, dd.dtype, F.FPCA_PREC_F32, dd.grid_cov, b.gamma, None, ds.k,
+        b.evals, b.fve = F.fpca_eig_randomized(hh, dd.dtype, panel_prec, dd.grid_cov, b.gamma, None, ds.k,
                                                ds.oversample, ds.power_iters, ds.rp_seed, b.efuns)
         if ev: ev[4].record(torch.cuda.current_stream())
 
@@ -505,7 +510,7 @@ def main():
         "config": {"workload": "d=2 common grid 64x64, n=%d Matern-1.5 GP fields, cov 64^4 nodes, h=0.1, "
                                "randomized eig k=20 p=10 q=2" % args.n,
                    "n": args.n, "grid": [64, 64], "cov_nodes": nodes, "h": ds.h_cov,
-                   "gram_prec": args.gram_prec},
+                   "gram_prec": args.gram_prec, "panel_prec": args.panel_prec},
         "stages_ms": stage_ms,
         "latency_ms_per_step": latency_ms,
         "pipelining": "steps alternate over two handles and buffer sets; step i+1's binning and smoothing run "

@@ -251,8 +251,13 @@ int fpca_smooth_cov(fpca_handle handle, const fpca_grid *grid, int dtype, const 
  *   gamma: P x P (P = prod grid->M) symmetric, `dtype`.
  *   quad_w: optional device array of P FP64 weights; NULL means the Riemann
  *     weights prod_k 1/(M_k-1), set to 0 outside the grid's mask.
- *   prec: FPCA_PREC_F64 (dtype F64) or FPCA_PREC_F32 (FP32 products of A with
- *     the basis, FP64 orthonormalization and Rayleigh-Ritz).
+ *   prec: FPCA_PREC_F64 (dtype F64); for dtype F32, FPCA_PREC_F32 (FP32
+ *     products of A with the basis) or FPCA_PREC_BF16X3 (the same products
+ *     with A and the basis split as x = hi + lo in bf16, hi*hi + hi*lo + lo*hi
+ *     with FP32 accumulation: relative error of each product entry of order
+ *     1e-5, eigenvalues within 1e-4 of the largest). The orthonormalization
+ *     and the Rayleigh-Ritz step are FP64 in every case. FPCA_PREC_BF16X3
+ *     reads gamma by rows (it must be exactly symmetric).
  *   k >= 1, oversample >= 0, k + oversample <= min(64, P).
  *   evals: host, k doubles. efuns: device, P x k column-major of `dtype`.
  *   fve: host, k doubles, or NULL. Synchronizes the handle's stream.

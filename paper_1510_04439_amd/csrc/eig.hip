@@ -153,6 +153,148 @@ __global__ __launch_bounds__(256) void k_panel_f32(int64_t P, const float *__res
   }
 }
 
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// The same partial products as k_panel_f32 on BF16x3 MFMA: each FP32 value x
+// is split as hi = bf16(x), lo = bf16(x - hi) while it is staged in LDS, and
+// a 16x16 block takes lo*hi + hi*lo + hi*hi on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation (the lo*lo term, below 2^-16 of the product, is dropped).
+// Gamma is symmetric, so the 64 output nodes p of a workgroup read their own
+// rows: thread (p, g) takes 8 consecutive nodes q of row p per 32 (one
+// 32-byte run), and the 16 rows of a wavefront's B operand come from LDS as
+// one 16-byte read per lane. Tiles of 64 nodes (two MFMA k-steps) in two LDS
+// buffers; the next tile waits in registers while this one is used. Rows
+// past P are read from row P - 1 and feed only outputs past P, which are not
+// written.
+template <int RB, bool VEC>
+__global__ __launch_bounds__(256) void k_panel_bf16x3(int64_t P, const float *__restrict__ G,
+                                                       const float *__restrict__ X, int64_t kchunk,
+                                                       float *__restrict__ part) {
+  constexpr int RP = RB * 16;
+  constexpr int KT = 64;
+  constexpr int LK = KT + 8;  // padded LDS row (144 bytes): the 16 rows of an operand read on distinct banks
+  constexpr int NX = (KT * RP / 4 + 255) / 256;  // float4s of the basis tile per thread
+  __shared__ __attribute__((aligned(16))) unsigned short Gs[2][2][64][LK];  // [buffer][hi, lo][p][q]
+  __shared__ __attribute__((aligned(16))) unsigned short Xs[2][2][RP][LK];  // [buffer][hi, lo][j][q]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c0 = int64_t(blockIdx.x) * 64;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(P, k0 + kchunk);
+  float4_t acc[2][RB];  // one set per k-step of a tile: independent MFMA chains
+#pragma unroll
+  for (int b = 0; b < RB; ++b) acc[0][b] = acc[1][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int gp = tid >> 2, gg = tid & 3;
+  const float *grow = G + min(c0 + gp, P - 1) * P;
+  float rg[2][8], rx[NX][4];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t q = kb + 32 * h + 8 * gg;
+      if (VEC && q + 8 <= k1) {
+        const float4 a = *reinterpret_cast<const float4 *>(grow + q);
+        const float4 b = *reinterpret_cast<const float4 *>(grow + q + 4);
+        rg[h][0] = a.x, rg[h][1] = a.y, rg[h][2] = a.z, rg[h][3] = a.w;
+        rg[h][4] = b.x, rg[h][5] = b.y, rg[h][6] = b.z, rg[h][7] = b.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rg[h][e] = q + e < k1 ? grow[q + e] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int o = tid + 256 * u;
+      const int64_t qq = kb + o / (RP / 4);
+      const int j4 = (o % (RP / 4)) * 4;
+      if (o < KT * RP / 4 && qq < k1) {
+        const float4 v = *reinterpret_cast<const float4 *>(X + qq * RP + j4);
+        rx[u][0] = v.x, rx[u][1] = v.y, rx[u][2] = v.z, rx[u][3] = v.w;
+      } else {
+        rx[u][0] = rx[u][1] = rx[u][2] = rx[u][3] = 0.f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u16x8 hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const unsigned short hb = bf16_rne(rg[h][e]);
+        hv[e] = hb;
+        lv[e] = bf16_rne(rg[h][e] - bf16_to_f32(hb));
+      }
+      *reinterpret_cast<u16x8 *>(&Gs[buf][0][gp][32 * h + 8 * gg]) = hv;
+      *reinterpret_cast<u16x8 *>(&Gs[buf][1][gp][32 * h + 8 * gg]) = lv;
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int o = tid + 256 * u;
+      if (o < KT * RP / 4) {
+        const int ql = o / (RP / 4), j4 = (o % (RP / 4)) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned short hb = bf16_rne(rx[u][e]);
+          Xs[buf][0][j4 + e][ql] = hb;
+          Xs[buf][1][j4 + e][ql] = bf16_rne(rx[u][e] - bf16_to_f32(hb));
+        }
+      }
+    }
+  };
+  auto rd = [](const unsigned short *p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p)); };
+  int buf = 0;
+  if (k0 < k1) {
+    load(k0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += KT) {
+    const bool more = kb + KT < k1;
+    if (more) load(kb + KT);
+    // lane l: node offset 8 (l / 16) of the k-step; B: node p = 16 wave + l % 16, A: basis column j = 16 mb + l % 16
+    bf16x8 bh[2], bl[2], ah[2][RB], al[2][RB];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int kq = 32 * s + 8 * (lane >> 4);
+      bh[s] = rd(&Gs[buf][0][wave * 16 + (lane & 15)][kq]);
+      bl[s] = rd(&Gs[buf][1][wave * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int mb = 0; mb < RB; ++mb) {
+        ah[s][mb] = rd(&Xs[buf][0][mb * 16 + (lane & 15)][kq]);
+        al[s][mb] = rd(&Xs[buf][1][mb * 16 + (lane & 15)][kq]);
+      }
+    }
+    // the three products of a block are 2 RB MFMAs apart
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int mb = 0; mb < RB; ++mb)
+        acc[s][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s][mb], bh[s], acc[s][mb], 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int mb = 0; mb < RB; ++mb)
+        acc[s][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s][mb], bl[s], acc[s][mb], 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int mb = 0; mb < RB; ++mb)
+        acc[s][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s][mb], bh[s], acc[s][mb], 0, 0, 0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // D[j][p]: row j = mb*16 + 4*(lane/16) + v, column p = c0 + wave*16 + lane%16.
+  const int64_t p = c0 + wave * 16 + (lane & 15);
+  if (p < P) {
+    float *dst = part + (int64_t(blockIdx.y) * P + p) * RP;
+#pragma unroll
+    for (int mb = 0; mb < RB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[mb * 16 + 4 * (lane >> 4) + v] = acc[0][mb][v] + acc[1][mb][v];
+  }
+}
+
 // FP64 product for FP64 storage (small grids): thread per (p, j); the Gamma
 // row stays in cache across the rp threads that share p.
 __global__ void k_panel_f64(int64_t P, int rp, const double *__restrict__ G, const double *__restrict__ X,
@@ -744,7 +886,7 @@ inline unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
 
 template <typename T, int RP>
 int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k, int r,
-            int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h, fpca_covop_s *op) {
+            int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h, fpca_covop_s *op, int prec) {
   const bool f32 = sizeof(T) == 4;
   // K split of the panel product: about two workgroups per compute unit
   // (fewer splits read fewer partials back; at P = 4096, 8 splits measured
@@ -795,13 +937,23 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
       dim3 grd((unsigned)colblocks, (unsigned)nsplit);
       const bool vec = (P % 4 == 0) && ((reinterpret_cast<uintptr_t>(gamma) & 15) == 0);
       constexpr int RB = RP / 16;
-      if (vec)
-        hipLaunchKernelGGL((k_panel_f32<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
-                           (const float *)X, kchunk, part);
-      else
-        hipLaunchKernelGGL((k_panel_f32<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
-                           (const float *)X, kchunk, part);
-      FPCA_LAUNCH_CHECK("panel_f32");
+      if (prec == FPCA_PREC_BF16X3) {
+        if (vec)
+          hipLaunchKernelGGL((k_panel_bf16x3<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                             (const float *)X, kchunk, part);
+        else
+          hipLaunchKernelGGL((k_panel_bf16x3<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                             (const float *)X, kchunk, part);
+        FPCA_LAUNCH_CHECK("panel_bf16x3");
+      } else {
+        if (vec)
+          hipLaunchKernelGGL((k_panel_f32<RB, true>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                             (const float *)X, kchunk, part);
+        else
+          hipLaunchKernelGGL((k_panel_f32<RB, false>), grd, dim3(256), 0, ctx->stream, P, (const float *)gamma,
+                             (const float *)X, kchunk, part);
+        FPCA_LAUNCH_CHECK("panel_f32");
+      }
     } else {
       if (op) {
         // the covariance operator: Gamma X without Gamma
@@ -885,13 +1037,17 @@ int eig_run(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma,
 template <typename T>
 int eig_impl(fpca_context *ctx, const fpca_grid *grid, int64_t P, const T *gamma, const double *quad_w, int k,
              int oversample, int power_iters, uint64_t seed, double *evals_h, T *efuns, double *fve_h,
-             fpca_covop_s *op = nullptr) {
+             fpca_covop_s *op = nullptr, int prec = FPCA_PREC_F64) {
   const int r = k + oversample;
   switch ((r + 15) / 16) {
-    case 1: return eig_run<T, 16>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
-    case 2: return eig_run<T, 32>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
-    case 3: return eig_run<T, 48>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
-    default: return eig_run<T, 64>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op);
+    case 1:
+      return eig_run<T, 16>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op, prec);
+    case 2:
+      return eig_run<T, 32>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op, prec);
+    case 3:
+      return eig_run<T, 48>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op, prec);
+    default:
+      return eig_run<T, 64>(ctx, grid, P, gamma, quad_w, k, r, power_iters, seed, evals_h, efuns, fve_h, op, prec);
   }
 }
 
@@ -924,14 +1080,15 @@ extern "C" int fpca_eig_randomized(fpca_handle ctx, int dtype, int prec, const f
   if (k + oversample > 64 || k + oversample > P)
     return set_error(FPCA_ERR_INVALID_ARG, "k + oversample = %d must be <= min(64, P)", k + oversample);
   if (dtype == FPCA_F64 && prec != FPCA_PREC_F64) return set_error(FPCA_ERR_UNSUPPORTED, "dtype F64 needs prec F64");
-  if (dtype == FPCA_F32 && prec != FPCA_PREC_F32) return set_error(FPCA_ERR_UNSUPPORTED, "dtype F32 needs prec F32");
+  if (dtype == FPCA_F32 && prec != FPCA_PREC_F32 && prec != FPCA_PREC_BF16X3)
+    return set_error(FPCA_ERR_UNSUPPORTED, "dtype F32 needs prec F32 or BF16X3");
   if (dtype != FPCA_F64 && dtype != FPCA_F32) return set_error(FPCA_ERR_INVALID_ARG, "bad dtype");
   if (int rc = set_device(ctx)) return rc;
   if (dtype == FPCA_F64)
     return eig_impl<double>(ctx, grid, P, static_cast<const double *>(gamma), quad_w, k, oversample, power_iters, seed,
                             evals, static_cast<double *>(efuns), fve);
   return eig_impl<float>(ctx, grid, P, static_cast<const float *>(gamma), quad_w, k, oversample, power_iters, seed,
-                         evals, static_cast<float *>(efuns), fve);
+                         evals, static_cast<float *>(efuns), fve, nullptr, prec);
 }
 
 extern "C" int fpca_eig_covop(fpca_covop op, const double *quad_w, int k, int oversample, int power_iters,

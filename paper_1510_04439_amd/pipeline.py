@@ -81,11 +81,14 @@ def alloc(dd: DeviceData, k: int, with_status: bool = True, analytic_C: bool = F
 
 def fit(h: B.Handle, dd: DeviceData, bufs: FitBuffers, h_mean: float, h_cov: float, k: int,
         oversample: int, power_iters: int, seed: int, prec: Optional[int] = None,
-        analytic_C: bool = False, do_eig: bool = True) -> FitBuffers:
-    """Queues the whole hot path; returns the buffers (eigenvalues on the host)."""
+        analytic_C: bool = False, do_eig: bool = True, eig_prec: Optional[int] = None) -> FitBuffers:
+    """Queues the whole hot path; returns the buffers (eigenvalues on the host).
+    prec: the binning products' precision; eig_prec: that of the range
+    finder's products (FP64 or FP32 storage precision when None)."""
     if prec is None:
         prec = B.FPCA_PREC_F64 if dd.dtype == B.FPCA_F64 else B.FPCA_PREC_F32
-    eig_prec = B.FPCA_PREC_F64 if dd.dtype == B.FPCA_F64 else B.FPCA_PREC_F32
+    if eig_prec is None:
+        eig_prec = B.FPCA_PREC_F64 if dd.dtype == B.FPCA_F64 else B.FPCA_PREC_F32
     B.fpca_bin(h, dd.grid_mean, B.FPCA_BIN_MEAN, dd.design, dd.dtype, prec, dd.n, dd.offsets, dd.t,
                dd.y, None, 0, bufs.c, bufs.s)
     B.fpca_smooth_mean(h, dd.grid_mean, dd.dtype, bufs.c, bufs.s, B.FPCA_K_EPANECHNIKOV, h_mean,

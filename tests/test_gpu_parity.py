@@ -509,6 +509,48 @@ def test_eig_basis_widths(torch, F, h, k, p, dt, rank):
         assert err <= 100 * tol * scale * np.abs(rphi[:, j]).max(), (j, err)
 
 
+@pytest.mark.parametrize("M,k,p,rank", [((24, 20), 6, 24, 0), ((24, 20), 10, 54, 0), ((23, 19), 8, 32, 0),
+                                          ((24, 20), 6, 24, 12), ((64, 64), 20, 10, 0)])
+def test_eig_bf16x3_products(torch, F, h, M, k, p, rank):
+    """FP32 surfaces with the products of A and the basis on BF16x3 MFMA
+    (k_panel_bf16x3), against the oracle's FP64 randomized eig. Grids: P = 480
+    (a partial 64-node column block), P = 437 (rows not 16-byte aligned: the
+    scalar loads), and the benchmark's P = 4096 with r = 30. Bars from the
+    split: each product drops lo*lo and rounds the lo parts, <= 3 2^-16 of
+    |x y| per term and about 2^-17 typically, so A Q carries a relative error
+    of order 1e-5 and the eigenvalues 1e-4 of the largest (the Gram product's
+    stated BF16x3 bound); eigenfunctions 1e-2 times the gap factor."""
+    _say(f"eig bf16x3 M={M} k={k} p={p} rank={rank}")
+    P = int(np.prod(M))
+    rng = np.random.default_rng(90 + P + k + rank)
+    nv = rank if rank else min(60, P // 4)
+    V = np.linalg.qr(rng.standard_normal((P, nv)))[0]
+    lam = 1.5 ** -np.arange(nv) if P < 1000 else (1.0 + np.arange(nv)) ** -2.0
+    Gam = (V * lam) @ V.T
+    if not rank:
+        E = rng.standard_normal((P, P)) * 1e-6
+        Gam = Gam + (E + E.T) / 2
+    Gam = Gam.astype(np.float32)
+    om = oracle.quad_weights(M, rule="trapezoid")
+    out = {}
+    for prec in (F.FPCA_PREC_BF16X3, F.FPCA_PREC_F32):
+        ef = torch.empty(k, P, dtype=torch.float32, device="cuda:0")
+        ev, fve = F.fpca_eig_randomized(h, F.FPCA_F32, prec, F.Grid(M), dev(torch, Gam), dev(torch, om), k, p, 2, 13,
+                                        ef)
+        out[prec] = (ev, fve, host(ef).T)
+    rev, rphi, rfve = oracle.eig_randomized(Gam.astype(np.float64), om, k, p, 2, 13)
+    ev, fve, phi = out[F.FPCA_PREC_BF16X3]
+    tol = 1e-4
+    assert np.abs(ev - rev).max() <= tol * np.abs(rev).max()
+    assert np.abs(fve - rfve).max() <= tol
+    assert np.abs(ev - out[F.FPCA_PREC_F32][0]).max() <= tol * np.abs(rev).max()
+    for j in range(k):
+        gap = min(abs(rev[j] - rev[j - 1]) if j else np.inf, abs(rev[j] - rev[j + 1]) if j + 1 < k else np.inf)
+        scale = max(1.0, 0.1 * rev[0] / gap) if np.isfinite(gap) else 1.0
+        err = min(np.abs(phi[:, j] - rphi[:, j]).max(), np.abs(phi[:, j] + rphi[:, j]).max())
+        assert err <= 100 * tol * scale * np.abs(rphi[:, j]).max(), (j, err)
+
+
 def test_eig_full_size(torch, F, h):
     """The benchmark's eig configuration at its full size: P = 64^2 = 4096 nodes,
     k = 20, oversample 10, two power iterations, FP32 surface (the launch
