@@ -149,6 +149,22 @@ int fpca_bin(fpca_handle handle, const fpca_grid *grid, int kind, int design, in
              int32_t *bin_index, int64_t *cell_count);
 
 /*
+ * fpca_bin_common -- both binnings of n complete common-grid curves (eqs. 2.3
+ * and 2.4) in one call: the results of fpca_bin(kind = FPCA_BIN_MEAN,
+ * FPCA_COMMON_GRID) into (mean_weights, mean_sums, mean_sq_sums) and of
+ * fpca_bin(kind = FPCA_BIN_COV, FPCA_COMMON_GRID) into (cov_weights,
+ * cov_sums), bit for bit. With dtype FPCA_F32 and prec FPCA_PREC_BF16X3 the
+ * Gram product's pass that splits Y into bf16 hi/lo also forms the mean's
+ * column sums, so Y (n x P) is read once for both; other combinations run
+ * the two binnings one after the other.
+ *   y: device, n x P row-major of `dtype`; mean_weights, mean_sums: P;
+ *   mean_sq_sums: P or NULL; cov_weights: P x P or NULL (the pair weights,
+ *   materialized only when given); cov_sums: P x P. Errors as fpca_bin.
+ */
+int fpca_bin_common(fpca_handle handle, const fpca_grid *grid, int dtype, int prec, int64_t n, const void *y,
+                    void *mean_weights, void *mean_sums, void *mean_sq_sums, void *cov_weights, void *cov_sums);
+
+/*
  * fpca_smooth_mean -- binned local-linear smoother of the mean (eq. 2.3):
  * at every node x, b0 of the weighted least-squares fit of the binned sums
  * with weights K((y-x)/h) and regressors (y-x)/h, solved in FP64:

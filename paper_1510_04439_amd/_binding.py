@@ -33,7 +33,7 @@ FPCA_ENGINE_AUTO, FPCA_ENGINE_QUEUE, FPCA_ENGINE_PASSES = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "fpca_create", "fpca_destroy", "fpca_set_stream", "fpca_sync", "fpca_last_error",
-    "fpca_bin", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
+    "fpca_bin", "fpca_bin_common", "fpca_smooth_mean", "fpca_smooth_cov", "fpca_eig_randomized", "fpca_rng_normal",
     "fpca_cv_batched", "fpca_bw_features", "fpca_bw_num_params", "fpca_bw_mlp_forward",
     "fpca_bw_mlp_backward", "fpca_bw_adam_step", "fpca_noise_variance", "fpca_pace_scores",
     "fpca_reconstruct", "fpca_pace_scores_noalloc", "fpca_cv_select", "fpca_cv_loo", "fpca_bw_search",
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     L.fpca_last_error.restype = ctypes.c_char_p
     L.fpca_bin.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i32, i32, i64, vp, vp, vp, vp, i32,
                            vp, vp, vp, vp, vp]
+    L.fpca_bin_common.argtypes = [vp, ctypes.POINTER(_GridC), i32, i32, i64, vp, vp, vp, vp, vp, vp]
     L.fpca_smooth_mean.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, vp, i32,
                                    ctypes.POINTER(ctypes.c_double), vp, vp]
     L.fpca_smooth_cov.argtypes = [vp, ctypes.POINTER(_GridC), i32, vp, ctypes.c_double, vp, vp, i32,
@@ -193,6 +194,13 @@ def fpca_stream_create_cu_range(device: int, cu_begin: int, cu_end: int) -> int:
 
 def fpca_stream_destroy(stream: int):
     _check(load_library().fpca_stream_destroy(ctypes.c_void_p(stream)))
+
+
+def fpca_bin_common(h: Handle, grid: Grid, dtype: int, prec: int, n: int, y, mean_weights, mean_sums,
+                    mean_sq_sums, cov_weights, cov_sums):
+    g = grid.c()
+    _check(load_library().fpca_bin_common(h.ptr, ctypes.byref(g), dtype, prec, int(n), _ptr(y), _ptr(mean_weights),
+                                          _ptr(mean_sums), _ptr(mean_sq_sums), _ptr(cov_weights), _ptr(cov_sums)))
 
 
 def fpca_bin(h: Handle, grid: Grid, kind: int, design: int, dtype: int, prec: int, n: int,

@@ -743,3 +743,52 @@ extern "C" int fpca_bin(fpca_handle ctx, const fpca_grid *grid, int kind, int de
                          static_cast<const float *>(y), fold_of_curve, n_folds, static_cast<float *>(weights),
                          static_cast<float *>(sums), static_cast<float *>(sq_sums), bin_index, cell_count);
 }
+
+// Both binnings of complete common-grid curves. FP32 data with BF16x3
+// products: the Gram product's split pass over Y also leaves the mean's FP64
+// column-sum chunks (the same sums as k_colsum, bit for bit), so Y is read
+// once; k_colsum_finish then forms the mean's arrays. Otherwise the two
+// binnings run one after the other.
+extern "C" int fpca_bin_common(fpca_handle ctx, const fpca_grid *grid, int dtype, int prec, int64_t n, const void *y,
+                               void *mean_weights, void *mean_sums, void *mean_sq_sums, void *cov_weights,
+                               void *cov_sums) {
+  if (int rc = check_handle(ctx)) return rc;
+  int64_t P;
+  if (int rc = check_grid(grid, &P)) return rc;
+  if (dtype != FPCA_F32 || prec != FPCA_PREC_BF16X3) {
+    if (int rc = fpca_bin(ctx, grid, FPCA_BIN_MEAN, FPCA_COMMON_GRID, dtype, prec, n, nullptr, nullptr, y, nullptr,
+                          0, mean_weights, mean_sums, mean_sq_sums, nullptr, nullptr))
+      return rc;
+    return fpca_bin(ctx, grid, FPCA_BIN_COV, FPCA_COMMON_GRID, dtype, prec, n, nullptr, nullptr, y, nullptr, 0,
+                    cov_weights, cov_sums, nullptr, nullptr, nullptr);
+  }
+  if (n < 0) return set_error(FPCA_ERR_INVALID_ARG, "n < 0");
+  if (!mean_weights || !mean_sums || !cov_sums)
+    return set_error(FPCA_ERR_INVALID_ARG, "mean_weights, mean_sums and cov_sums are required");
+  if (!y && n > 0) return set_error(FPCA_ERR_INVALID_ARG, "y is required");
+  if (P > 8192) return set_error(FPCA_ERR_UNSUPPORTED, "covariance binning needs P <= 8192 (P = %lld)", (long long)P);
+  if (int rc = set_device(ctx)) return rc;
+  const float *Y = static_cast<const float *>(y);
+  float *W = static_cast<float *>(mean_weights), *S = static_cast<float *>(mean_sums);
+  float *SQ = static_cast<float *>(mean_sq_sums);
+  const int nchunks = int((n + 63) / 64);  // the Gram split's 64-row K blocks
+  const size_t part = carve_bytes(size_t(nchunks > 0 ? nchunks : 1) * P, 8);
+  if (int rc = ws_reserve(ctx, 2 * part)) return rc;
+  Carver cv{static_cast<char *>(ctx->ws), 0, ctx->ws_size};
+  double *part1 = cv.take<double>(size_t(nchunks > 0 ? nchunks : 1) * P);
+  double *part2 = cv.take<double>(size_t(nchunks > 0 ? nchunks : 1) * P);
+  const double w = 1.0 / (double(P) * double(P - 1));
+  if (int rc = syrk_f32(ctx, Y, n, P, static_cast<float *>(cov_sums), P, float(w), true, FPCA_PREC_BF16X3, part1,
+                        SQ ? part2 : nullptr))
+    return rc;
+  hipLaunchKernelGGL(k_colsum_finish<float>, dim3(unsigned((8 * P + 255) / 256)), dim3(256), 0, ctx->stream, n, P,
+                     nchunks, part1, part2, W, S, SQ);
+  FPCA_LAUNCH_CHECK("colsum_finish");
+  if (cov_weights) {
+    float *CW = static_cast<float *>(cov_weights);
+    if (int rc = fill_f32(ctx, CW, float(double(n) * w), P * P)) return rc;
+    hipLaunchKernelGGL(k_set_diag<float>, dim3(grid1(P)), dim3(256), 0, ctx->stream, CW, P, 0.f);
+    FPCA_LAUNCH_CHECK("set_diag");
+  }
+  return FPCA_OK;
+}

@@ -136,8 +136,11 @@ int fill_bytes_zero(fpca_context *ctx, void *p, int64_t nbytes);
 // Symmetric rank-k product C = A^T A (A: K x N row-major, ld = N), written to
 // both triangles of the N x N output with ldc, scaled by `alpha`; entries on
 // the diagonal set to `diag_value` if zero_diag. FP32 operands on MFMA.
+// prec = FPCA_PREC_BF16X3 with colsum given: the pass that splits A also
+// leaves FP64 column sums of A (and of its squares, with colsq) per chunk of
+// 64 rows at colsum[chunk][N] (ceil(K / 64) chunks).
 int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, int64_t ldc,
-             float alpha, bool zero_diag, int prec);
+             float alpha, bool zero_diag, int prec, double *colsum = nullptr, double *colsq = nullptr);
 int syrk_f64(fpca_context *ctx, const double *A, int64_t K, int64_t N, double *C, int64_t ldc,
              double alpha, bool zero_diag);
 

@@ -162,9 +162,17 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ A, i
 // rows padded with zeros to Kp (a multiple of 64). 64x64 tiles through LDS.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
+//
+// With cs1 (and cs2) given, the same pass also leaves the column sums (and
+// sums of squares) of its 64 rows in FP64 at cs1[blockIdx.y][n]: four
+// groups of 16 consecutive rows, each added in row order, then combined as
+// (g0 + g1) + (g2 + g3) -- the chunk sums of the mean's column-sum kernel,
+// bit for bit.
 __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, int64_t K, int64_t N, int64_t Kp,
-                                                  unsigned short *__restrict__ Th, unsigned short *__restrict__ Tl) {
+                                                  unsigned short *__restrict__ Th, unsigned short *__restrict__ Tl,
+                                                  double *__restrict__ cs1, double *__restrict__ cs2) {
   __shared__ float tile[64][65];
+  __shared__ double red[2][4][64];
   const int64_t n0 = int64_t(blockIdx.x) * 64, k0 = int64_t(blockIdx.y) * 64;
   // 16 threads per input row, four consecutive n each (16-byte loads where aligned)
   const int q4 = (threadIdx.x & 15) * 4, ty = threadIdx.x >> 4;
@@ -183,6 +191,25 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ A, in
     }
   }
   __syncthreads();
+  if (cs1) {
+    const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double sm = 0.0, sq = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double x = double(tile[16 * g + u][cc]);
+      sm += x;
+      sq += x * x;
+    }
+    red[0][g][cc] = sm;
+    red[1][g][cc] = sq;
+    __syncthreads();
+    if (threadIdx.x < 64 && n0 + threadIdx.x < N) {
+      const int64_t o = int64_t(blockIdx.y) * N + n0 + threadIdx.x;
+      const int c = threadIdx.x;
+      cs1[o] = (red[0][0][c] + red[0][1][c]) + (red[0][2][c] + red[0][3][c]);
+      if (cs2) cs2[o] = (red[1][0][c] + red[1][1][c]) + (red[1][2][c] + red[1][3][c]);
+    }
+  }
   // thread -> output row n0 + tid/4, two runs of eight k (16-byte stores)
   const int rn = threadIdx.x >> 2;
   const int64_t n = n0 + rn;
@@ -547,7 +574,7 @@ __global__ __launch_bounds__(256) void k_gram_valu(const Tin *__restrict__ A, in
 }  // namespace
 
 int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, int64_t ldc, float alpha,
-             bool zero_diag, int prec) {
+             bool zero_diag, int prec, double *colsum, double *colsq) {
   if (N <= 0) return FPCA_OK;
   const int nb = int((N + TB - 1) / TB);
   const int tiles = nb * (nb + 1) / 2;
@@ -590,7 +617,7 @@ int syrk_f32(fpca_context *ctx, const float *A, int64_t K, int64_t N, float *C, 
       return FPCA_OK;
     }
     dim3 gs((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
-    hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl);
+    hipLaunchKernelGGL(k_split_t, gs, dim3(256), 0, ctx->stream, A, K, N, Kp, Th, Tl, colsum, colsq);
     FPCA_LAUNCH_CHECK("split_t");
     const int vec4 = (ldc % 4 == 0) && ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
     hipLaunchKernelGGL(k_syrk_bf16x3, dim3(unsigned(G)), dim3(256), 0, ctx->stream, Th, Tl, Kp, N, C, ldc, alpha,

@@ -196,6 +196,49 @@ def test_bin_cov_common_grid_bf16x3_full(torch, F, h, M, n):
     assert normwise_rel(Gh[p, q], ref) < 1e-4
 
 
+@pytest.mark.parametrize("M,n,dt,prec", [((20, 13), 333, "f32", "bf16x3"), ((64, 64), 5000, "f32", "bf16x3"),
+                                          ((61, 71), 777, "f32", "bf16x3"), ((7, 9), 1, "f32", "bf16x3"),
+                                          ((7, 9), 0, "f32", "bf16x3"), ((20, 13), 333, "f32", "f32"),
+                                          ((7, 9), 70, "f64", "f64")])
+def test_bin_common_one_pass(torch, F, h, M, n, dt, prec):
+    """fpca_bin_common against fpca_bin(MEAN) and fpca_bin(COV) on the same
+    curves, bit for bit (FP32 data with BF16x3 products: the mean's column
+    sums come from the Gram product's split pass, in the same chunks and the
+    same order of addition; other precisions run the two calls), and the
+    mean's sums against the oracle. P = 4331 is odd (scalar loads in the
+    split); n = 777 leaves a ragged 64-row chunk; n = 1 and n = 0 are the
+    edges (a zero Gram product, no chunks)."""
+    _say(f"bin_common M={M} n={n} {dt} {prec}")
+    rng = np.random.default_rng(5 + n)
+    P = int(np.prod(M))
+    npdt, tdt = (np.float32, torch.float32) if dt == "f32" else (np.float64, torch.float64)
+    dty = F.FPCA_F32 if dt == "f32" else F.FPCA_F64
+    pr = {"bf16x3": F.FPCA_PREC_BF16X3, "f32": F.FPCA_PREC_F32, "f64": F.FPCA_PREC_F64}[prec]
+    Y = rng.standard_normal((max(n, 1), P)).astype(npdt)[:n]
+    Yd = dev(torch, Y).to(tdt) if n else torch.empty(0, P, dtype=tdt, device="cuda:0")
+    z = lambda *sh: torch.full(sh, float("nan"), dtype=tdt, device="cuda:0")
+    c1, s1, q1, C1, G1 = z(P), z(P), z(P), z(P, P), z(P, P)
+    F.fpca_bin_common(h, F.Grid(M), dty, pr, n, Yd, c1, s1, q1, C1, G1)
+    c2, s2, q2, C2, G2 = z(P), z(P), z(P), z(P, P), z(P, P)
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_MEAN, F.FPCA_COMMON_GRID, dty, pr, n, None, None, Yd, None, 0, c2, s2, q2)
+    F.fpca_bin(h, F.Grid(M), F.FPCA_BIN_COV, F.FPCA_COMMON_GRID, dty, pr, n, None, None, Yd, None, 0, C2, G2)
+    # without the optional outputs (no sums of squares, pair weights not materialized)
+    c3, s3, G3 = z(P), z(P), z(P, P)
+    F.fpca_bin_common(h, F.Grid(M), dty, pr, n, Yd, c3, s3, None, None, G3)
+    h.sync()
+    for a, b in ((c1, c2), (s1, s2), (q1, q2), (C1, C2), (G1, G2), (c3, c2), (s3, s2), (G3, G2)):
+        assert np.array_equal(host(a), host(b))
+    if n:
+        Y64 = Y.astype(np.float64)
+        rc, rs, _, _ = oracle.bin_common_grid(Y64)
+        rq = oracle.bin_common_grid(Y64 ** 2)[1]
+        tol = 1e-6 if dt == "f32" else 1e-13
+        assert normwise_rel(host(s1), rs) < tol and normwise_rel(host(q1), rq) < tol
+        assert normwise_rel(host(c1), rc) < tol
+    else:
+        assert np.all(host(G1) == 0) and np.all(host(s1) == 0)
+
+
 def test_domain_error_reported(torch, F, h):
     _say("domain")
     off = np.array([0, 3], np.int64)
