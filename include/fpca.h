@@ -122,7 +122,9 @@ const char *fpca_last_error(void);
  *   sq_sums[p,q] = ... times (Y_ij Y_il)^2  (optional; used by cross-validation)
  *   With folds (fold_of_curve != NULL, n_folds >= 1) each of these arrays holds
  *   n_folds+1 consecutive P x P slabs: slab 0 over all curves, slab f+1 over the
- *   curves of fold f only.
+ *   curves of fold f only. Such a call waits for the handle's stream once (it
+ *   reads the n_folds+1 fold boundaries back to size each fold's product), so
+ *   it cannot be captured in a graph; without folds nothing synchronizes.
  *
  * design = FPCA_IRREGULAR: offsets[n+1] (int64, offsets[0] = 0, nondecreasing)
  *   delimit curve i's observations; t is N x d row-major and y has N entries,
