@@ -164,7 +164,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // rows: thread (p, g) takes 8 consecutive nodes q of row p per 32 (one
 // 32-byte run), and the 16 rows of a wavefront's B operand come from LDS as
 // one 16-byte read per lane. Tiles of 64 nodes (two MFMA k-steps) in two LDS
-// buffers; the next tile waits in registers while this one is used. Rows
+// buffers, loaded into registers two tiles ahead of their products. Rows
 // past P are read from row P - 1 and feed only outputs past P, which are not
 // written.
 template <int RB, bool VEC>
@@ -186,43 +186,54 @@ __global__ __launch_bounds__(256) void k_panel_bf16x3(int64_t P, const float *__
   for (int b = 0; b < RB; ++b) acc[0][b] = acc[1][b] = float4_t{0.f, 0.f, 0.f, 0.f};
   const int gp = tid >> 2, gg = tid & 3;
   const float *grow = G + min(c0 + gp, P - 1) * P;
-  float rg[2][8], rx[NX][4];
-  auto load = [&](int64_t kb) {
+  // a tile's raw values in registers: g = this thread's two 8-node runs of
+  // its Gamma row, x = its float4s of the basis
+  static_assert(KT * RP / 4 == NX * 256, "every thread loads NX float4s of the basis tile");
+  // whole tiles (the same test in every lane): plain vector loads, so no lane
+  // writes the registers of a load still in flight; the ragged last tile of a
+  // chunk: scalar loads with the nodes past k1 read as 0
+  auto load = [&](int64_t kb, float (&g)[2][8], float (&x)[NX][4]) {
+    if (VEC && kb + KT <= k1) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t q = kb + 32 * h + 8 * gg;
-      if (VEC && q + 8 <= k1) {
+      for (int h = 0; h < 2; ++h) {
+        const int64_t q = kb + 32 * h + 8 * gg;
         const float4 a = *reinterpret_cast<const float4 *>(grow + q);
         const float4 b = *reinterpret_cast<const float4 *>(grow + q + 4);
-        rg[h][0] = a.x, rg[h][1] = a.y, rg[h][2] = a.z, rg[h][3] = a.w;
-        rg[h][4] = b.x, rg[h][5] = b.y, rg[h][6] = b.z, rg[h][7] = b.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) rg[h][e] = q + e < k1 ? grow[q + e] : 0.f;
+        g[h][0] = a.x, g[h][1] = a.y, g[h][2] = a.z, g[h][3] = a.w;
+        g[h][4] = b.x, g[h][5] = b.y, g[h][6] = b.z, g[h][7] = b.w;
       }
-    }
 #pragma unroll
-    for (int u = 0; u < NX; ++u) {
-      const int o = tid + 256 * u;
-      const int64_t qq = kb + o / (RP / 4);
-      const int j4 = (o % (RP / 4)) * 4;
-      if (o < KT * RP / 4 && qq < k1) {
-        const float4 v = *reinterpret_cast<const float4 *>(X + qq * RP + j4);
-        rx[u][0] = v.x, rx[u][1] = v.y, rx[u][2] = v.z, rx[u][3] = v.w;
-      } else {
-        rx[u][0] = rx[u][1] = rx[u][2] = rx[u][3] = 0.f;
+      for (int u = 0; u < NX; ++u) {
+        const int o = tid + 256 * u;
+        const float4 v = *reinterpret_cast<const float4 *>(X + (kb + o / (RP / 4)) * RP + (o % (RP / 4)) * 4);
+        x[u][0] = v.x, x[u][1] = v.y, x[u][2] = v.z, x[u][3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t q = kb + 32 * h + 8 * gg;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[h][e] = q + e < k1 ? grow[q + e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < NX; ++u) {
+        const int o = tid + 256 * u;
+        const int64_t qq = kb + o / (RP / 4);
+        const int j4 = (o % (RP / 4)) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[u][e] = qq < k1 ? X[qq * RP + j4 + e] : 0.f;
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const float (&g)[2][8], const float (&x)[NX][4]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       u16x8 hv, lv;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const unsigned short hb = bf16_rne(rg[h][e]);
+        const unsigned short hb = bf16_rne(g[h][e]);
         hv[e] = hb;
-        lv[e] = bf16_rne(rg[h][e] - bf16_to_f32(hb));
+        lv[e] = bf16_rne(g[h][e] - bf16_to_f32(hb));
       }
       *reinterpret_cast<u16x8 *>(&Gs[buf][0][gp][32 * h + 8 * gg]) = hv;
       *reinterpret_cast<u16x8 *>(&Gs[buf][1][gp][32 * h + 8 * gg]) = lv;
@@ -230,28 +241,18 @@ __global__ __launch_bounds__(256) void k_panel_bf16x3(int64_t P, const float *__
 #pragma unroll
     for (int u = 0; u < NX; ++u) {
       const int o = tid + 256 * u;
-      if (o < KT * RP / 4) {
-        const int ql = o / (RP / 4), j4 = (o % (RP / 4)) * 4;
+      const int ql = o / (RP / 4), j4 = (o % (RP / 4)) * 4;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const unsigned short hb = bf16_rne(rx[u][e]);
-          Xs[buf][0][j4 + e][ql] = hb;
-          Xs[buf][1][j4 + e][ql] = bf16_rne(rx[u][e] - bf16_to_f32(hb));
-        }
+      for (int e = 0; e < 4; ++e) {
+        const unsigned short hb = bf16_rne(x[u][e]);
+        Xs[buf][0][j4 + e][ql] = hb;
+        Xs[buf][1][j4 + e][ql] = bf16_rne(x[u][e] - bf16_to_f32(hb));
       }
     }
   };
   auto rd = [](const unsigned short *p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p)); };
-  int buf = 0;
-  if (k0 < k1) {
-    load(k0);
-    store(0);
-  }
-  __syncthreads();
-  for (int64_t kb = k0; kb < k1; kb += KT) {
-    const bool more = kb + KT < k1;
-    if (more) load(kb + KT);
-    // lane l: node offset 8 (l / 16) of the k-step; B: node p = 16 wave + l % 16, A: basis column j = 16 mb + l % 16
+  // lane l: node offset 8 (l / 16) of the k-step; B: node p = 16 wave + l % 16, A: basis column j = 16 mb + l % 16
+  auto mma = [&](int buf) {
     bf16x8 bh[2], bl[2], ah[2][RB], al[2][RB];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -280,9 +281,28 @@ __global__ __launch_bounds__(256) void k_panel_bf16x3(int64_t P, const float *__
 #pragma unroll
       for (int mb = 0; mb < RB; ++mb)
         acc[s][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s][mb], bh[s], acc[s][mb], 0, 0, 0);
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+  };
+  // Two register sets, two tiles ahead: while tile kb is multiplied from LDS
+  // buffer 0, tile kb + KT waits in set B and tile kb + 2 KT is loading into
+  // set A (then the same with the buffers and sets exchanged), so each
+  // workgroup keeps two tiles of Gamma in flight.
+  float ga[2][8], xa[NX][4], gb[2][8], xb[NX][4];
+  if (k0 < k1) {
+    load(k0, ga, xa);
+    if (k0 + KT < k1) load(k0 + KT, gb, xb);
+    store(0, ga, xa);
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += 2 * KT) {
+    if (kb + 2 * KT < k1) load(kb + 2 * KT, ga, xa);
+    mma(0);
+    if (kb + KT >= k1) break;
+    store(1, gb, xb);
+    __syncthreads();  // buffer 1 written; every wavefront is past buffer 0's products
+    if (kb + 3 * KT < k1) load(kb + 3 * KT, gb, xb);
+    mma(1);
+    if (kb + 2 * KT < k1) store(0, ga, xa);
+    __syncthreads();  // buffer 0 written; every wavefront is past buffer 1's products
   }
   // D[j][p]: row j = mb*16 + 4*(lane/16) + v, column p = c0 + wave*16 + lane%16.
   const int64_t p = c0 + wave * 16 + (lane & 15);
