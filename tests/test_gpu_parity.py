@@ -199,7 +199,8 @@ def test_bin_cov_common_grid_bf16x3_full(torch, F, h, M, n):
 @pytest.mark.parametrize("M,n,dt,prec", [((20, 13), 333, "f32", "bf16x3"), ((64, 64), 5000, "f32", "bf16x3"),
                                           ((61, 71), 777, "f32", "bf16x3"), ((7, 9), 1, "f32", "bf16x3"),
                                           ((7, 9), 0, "f32", "bf16x3"), ((20, 13), 333, "f32", "f32"),
-                                          ((7, 9), 70, "f64", "f64")])
+                                          ((7, 9), 70, "f64", "f64"), ((2, 2), 200, "f32", "bf16x3"),
+                                          ((4, 4), 65, "f32", "bf16x3"), ((4, 4), 64, "f32", "bf16x3")])
 def test_bin_common_one_pass(torch, F, h, M, n, dt, prec):
     """fpca_bin_common against fpca_bin(MEAN) and fpca_bin(COV) on the same
     curves, bit for bit (FP32 data with BF16x3 products: the mean's column
@@ -207,7 +208,9 @@ def test_bin_common_one_pass(torch, F, h, M, n, dt, prec):
     same order of addition; other precisions run the two calls), and the
     mean's sums against the oracle. P = 4331 is odd (scalar loads in the
     split); n = 777 leaves a ragged 64-row chunk; n = 1 and n = 0 are the
-    edges (a zero Gram product, no chunks)."""
+    edges (a zero Gram product, no chunks); P = 4 and 16 are far below one
+    128-node tile (rows past P read from row P - 1), n = 64 and 65 put the
+    curves exactly at and one past a 64-row step."""
     _say(f"bin_common M={M} n={n} {dt} {prec}")
     rng = np.random.default_rng(5 + n)
     P = int(np.prod(M))
@@ -553,12 +556,13 @@ def test_eig_basis_widths(torch, F, h, k, p, dt, rank):
 
 
 @pytest.mark.parametrize("M,k,p,rank", [((24, 20), 6, 24, 0), ((24, 20), 10, 54, 0), ((23, 19), 8, 32, 0),
-                                          ((24, 20), 6, 24, 12), ((64, 64), 20, 10, 0)])
+                                          ((24, 20), 6, 24, 12), ((64, 64), 20, 10, 0), ((9, 7), 3, 5, 0)])
 def test_eig_bf16x3_products(torch, F, h, M, k, p, rank):
     """FP32 surfaces with the products of A and the basis on BF16x3 MFMA
     (k_panel_bf16x3), against the oracle's FP64 randomized eig. Grids: P = 480
     (a partial 64-node column block), P = 437 (rows not 16-byte aligned: the
-    scalar loads), and the benchmark's P = 4096 with r = 30. Bars from the
+    scalar loads), the benchmark's P = 4096 with r = 30, and P = 63 with a
+    16-column basis (one 64-node column block, one K chunk). Bars from the
     split: each product drops lo*lo and rounds the lo parts, <= 3 2^-16 of
     |x y| per term and about 2^-17 typically, so A Q carries a relative error
     of order 1e-5 and the eigenvalues 1e-4 of the largest (the Gram product's
