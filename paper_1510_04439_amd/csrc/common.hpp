@@ -34,6 +34,10 @@ struct fpca_context {
   // Device-side error flags (bit 0: an observation outside [0,1]^d or NaN).
   int *d_flags = nullptr;
   int *h_flags = nullptr;  // pinned mirror
+  // d_flags[16], d_flags[17]: the two flags of the PACE right-hand-side
+  // kernel; zero between calls (each call's last kernel clears them), and
+  // false here while a call that set them may not have cleared them yet.
+  bool pace_flags_clean = true;
   // Pinned staging for small device-to-host results (eigenvalues and FVE).
   static constexpr size_t kStageBytes = 4096;
   double *h_stage = nullptr;

@@ -243,15 +243,18 @@ __device__ void cg_inverse(int k, const PaceDiag &dg, const double *__restrict__
 // shared inverse times the right-hand sides. Workgroups 1..CG_NGW form
 // partial sums of the shared matrix (cg_gram_part) and count themselves on
 // ready[1]; workgroup 0 adds them, inverts the matrix (cg_inverse) and
-// publishes the inverse through ready[0] (both cleared by k_pace_clear before
-// the launch), while the others form their right-hand sides. A workgroup that
+// publishes the inverse through ready[0] (both zero at the launch: k_pace
+// clears them at the end of every call), while the others form their
+// right-hand sides. A workgroup that
 // finds a flag unset after its spin limit gives up the shared factor: its
 // curves go to k_pace.
 constexpr int RH_CURVES = 16;
 
 // Clears the flag through which k_pace_cg_rhs publishes the shared inverse
 // and the count of its partial sums (a kernel rather than a memset, so that
-// the call can be captured in a graph).
+// the call can be captured in a graph). The flags start at zero and every
+// call's k_pace clears them again, so this runs only after a call that was
+// cut short between its two kernels.
 __global__ void k_pace_clear(int *__restrict__ ready) {
   if (threadIdx.x < 2) ready[threadIdx.x] = 0;
 }
@@ -441,7 +444,9 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
                                                        const T *__restrict__ y, const T *__restrict__ mu,
                                                        const T *__restrict__ efuns, int k, PaceDiag dg,
                                                        const double *__restrict__ Lcg, const int *__restrict__ cg_ok,
-                                                       T *__restrict__ scores) {
+                                                       T *__restrict__ scores, int *__restrict__ ready) {
+  // k_pace_cg_rhs has finished: its two flags return to zero for the next call
+  if (ready && blockIdx.x == 0 && threadIdx.x < 2) ready[threadIdx.x] = 0;
   __shared__ double ph[PACE_CH][PACE_KMAX + 1];
   __shared__ double yc[PACE_CH];
   __shared__ double A[PACE_KMAX][PACE_KMAX + 1];
@@ -571,6 +576,15 @@ __global__ __launch_bounds__(PACE_THREADS) void k_pace(GridDims g, int64_t n, in
 constexpr size_t PACE_PART_BYTES = size_t(CG_NGW) * 3 * 256 * sizeof(double);
 constexpr size_t PACE_SCRATCH_BYTES = PACE_KMAX * PACE_KMAX * sizeof(double) + 256 + 256 + PACE_PART_BYTES;
 
+// One copy per GPU of the scratch used by fpca_pace_scores_noalloc. In host
+// code `scratch` names a host-side stand-in: kernels get the device address
+// looked up for each device by pace_scratch_init.
+constexpr int PACE_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[PACE_MAX_DEVICES] = {};
+// the fixed array's two flags are zero (as they start): see pace_flags_clean
+bool g_scratch_clean[PACE_MAX_DEVICES] = {};
+
 // `fixed`: caller-provided scratch of PACE_SCRATCH_BYTES (the allocation-free
 // entry point), or NULL to carve it from the handle's arena.
 template <typename T>
@@ -580,19 +594,29 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
   const GridDims g = make_dims(grid);
   const double *Lcg = nullptr;
   const int *cg_ok = nullptr;
+  int *ready_out = nullptr;   // the flags k_pace clears (common grid)
+  bool *clean_out = nullptr;  // set again once that k_pace is queued
   if (design == FPCA_COMMON_GRID) {
     if (!fixed)
       if (int rc = ws_reserve(ctx, PACE_SCRATCH_BYTES)) return rc;
     Carver cv{static_cast<char *>(fixed ? fixed : ctx->ws), 0, fixed ? PACE_SCRATCH_BYTES : ctx->ws_size};
     double *L = cv.take<double>(PACE_KMAX * PACE_KMAX);
     int *okf = cv.take<int>(1);
-    int *ready = cv.take<int>(2);
+    int *ready_fixed = cv.take<int>(2);
+    // the flags: in the fixed array, or in the handle's flag words
+    int *ready = fixed ? ready_fixed : ctx->d_flags + 16;
+    bool *clean = fixed ? &g_scratch_clean[ctx->device] : &ctx->pace_flags_clean;
     double *gpart = cv.take<double>(PACE_PART_BYTES / sizeof(double));
     // vector loads when every row starts on a 16-byte boundary
     const bool vec = g.P % 4 == 0 && (reinterpret_cast<uintptr_t>(efuns) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
-    hipLaunchKernelGGL(k_pace_clear, dim3(1), dim3(64), 0, ctx->stream, ready);
-    FPCA_LAUNCH_CHECK("pace_clear");
+    if (!*clean) {
+      hipLaunchKernelGGL(k_pace_clear, dim3(1), dim3(64), 0, ctx->stream, ready);
+      FPCA_LAUNCH_CHECK("pace_clear");
+    }
+    *clean = false;
+    ready_out = ready;
+    clean_out = clean;
     Lcg = L;
     cg_ok = okf;
     // workgroup 0 inverts the shared matrix, the next CG_NGW form its partial
@@ -610,8 +634,9 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
   // (k_pace_cg_rhs solved them) and a workgroup only checks their marker
   const unsigned blocks = unsigned(n < 2048 ? n : 2048);
   hipLaunchKernelGGL(k_pace<T>, dim3(blocks), dim3(PACE_THREADS), 0, ctx->stream, g, n, design, offsets, t, y, mu,
-                     efuns, k, dg, Lcg, cg_ok, scores);
+                     efuns, k, dg, Lcg, cg_ok, scores, ready_out);
   FPCA_LAUNCH_CHECK("pace");
+  if (clean_out) *clean_out = true;
   return FPCA_OK;
 }
 
@@ -657,12 +682,6 @@ int reconstruct_impl(fpca_context *ctx, int64_t P, int64_t n, int k, const T *mu
   return FPCA_OK;
 }
 
-// One copy per GPU of the scratch used by fpca_pace_scores_noalloc. In host
-// code `scratch` names a host-side stand-in: kernels get the device address
-// looked up for each device by pace_scratch_init.
-constexpr int PACE_MAX_DEVICES = 64;
-std::mutex g_scratch_mu;
-void *g_scratch_ptr[PACE_MAX_DEVICES] = {};
 
 }  // namespace
 
@@ -679,6 +698,7 @@ int pace_scratch_init(int device) {
   FPCA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
   if (!ptr) return set_error(FPCA_ERR_DEVICE, "no device address for the PACE scratch");
   g_scratch_ptr[device] = ptr;
+  g_scratch_clean[device] = true;  // a __device__ array starts zeroed
   return FPCA_OK;
 }
 
