@@ -642,30 +642,35 @@ int pace_impl(fpca_context *ctx, const fpca_grid *grid, int design, int64_t n, c
 
 // Reconstruction on the grid (the display after eq. 2.7):
 //   xhat[i][p] = mu[p] + sum_l xi[i][l] phi_l[p].
-// Thread per node p of a 256-node block with its k basis values in registers;
-// the block's RC_CURVES score rows in LDS; writes are contiguous along p.
-constexpr int RC_CURVES = 16;
+// Thread per node p of a 256-node block with its k basis values in registers
+// (KB of them: k rounded up to a multiple of 8, the rest zero), the block's
+// RC_CURVES score rows in LDS (zero past k); writes are contiguous along p.
+// 64 curves per block: each block reads its nodes' basis values once per 64
+// output rows.
+constexpr int RC_CURVES = 64;
 
-template <typename T>
+template <typename T, int KB>
 __global__ __launch_bounds__(256) void k_reconstruct(int64_t P, int64_t n, int k, const T *__restrict__ mu,
                                                      const T *__restrict__ efuns, const T *__restrict__ xi,
                                                      T *__restrict__ xhat) {
-  __shared__ double xs[RC_CURVES][PACE_KMAX];
+  __shared__ double xs[RC_CURVES][KB];
   const int64_t i0 = int64_t(blockIdx.y) * RC_CURVES;
   const int nc = int(min(int64_t(RC_CURVES), n - i0));
-  for (int e = threadIdx.x; e < nc * k; e += blockDim.x) xs[e / k][e % k] = double(xi[(i0 + e / k) * k + e % k]);
+  for (int e = threadIdx.x; e < nc * KB; e += blockDim.x) {
+    const int c = e / KB, l = e % KB;
+    xs[c][l] = l < k ? double(xi[(i0 + c) * k + l]) : 0.0;
+  }
   __syncthreads();
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  double ph[PACE_KMAX];
+  double ph[KB];
 #pragma unroll
-  for (int l = 0; l < PACE_KMAX; ++l) ph[l] = l < k ? double(efuns[int64_t(l) * P + p]) : 0.0;
+  for (int l = 0; l < KB; ++l) ph[l] = l < k ? double(efuns[int64_t(l) * P + p]) : 0.0;
   const double m = double(mu[p]);
   for (int c = 0; c < nc; ++c) {
     double v = m;
 #pragma unroll
-    for (int l = 0; l < PACE_KMAX; ++l)
-      if (l < k) v += xs[c][l] * ph[l];
+    for (int l = 0; l < KB; ++l) v = fma(xs[c][l], ph[l], v);
     xhat[(i0 + c) * P + p] = T(v);
   }
 }
@@ -676,8 +681,22 @@ int reconstruct_impl(fpca_context *ctx, int64_t P, int64_t n, int k, const T *mu
   if (n == 0 || P == 0) return FPCA_OK;
   const int64_t gy = (n + RC_CURVES - 1) / RC_CURVES;
   if (gy > 65535) return set_error(FPCA_ERR_UNSUPPORTED, "n = %lld curves exceeds %d", (long long)n, 65535 * RC_CURVES);
-  hipLaunchKernelGGL(k_reconstruct<T>, dim3(unsigned((P + 255) / 256), unsigned(gy)), dim3(256), 0, ctx->stream, P,
-                     n, k, mu, efuns, xi, xhat);
+  const dim3 grid(unsigned((P + 255) / 256), unsigned(gy));
+  switch ((k + 7) / 8) {
+    case 1:
+      hipLaunchKernelGGL((k_reconstruct<T, 8>), grid, dim3(256), 0, ctx->stream, P, n, k, mu, efuns, xi, xhat);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_reconstruct<T, 16>), grid, dim3(256), 0, ctx->stream, P, n, k, mu, efuns, xi, xhat);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_reconstruct<T, 24>), grid, dim3(256), 0, ctx->stream, P, n, k, mu, efuns, xi, xhat);
+      break;
+    default:
+      hipLaunchKernelGGL((k_reconstruct<T, PACE_KMAX>), grid, dim3(256), 0, ctx->stream, P, n, k, mu, efuns, xi,
+                         xhat);
+      break;
+  }
   FPCA_LAUNCH_CHECK("reconstruct");
   return FPCA_OK;
 }

@@ -154,7 +154,8 @@ def test_pace_argument_errors(torch, F, h):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("P,n,k", [(300, 37, 7), (4096, 50, 20), (17, 1, 32)])
+@pytest.mark.parametrize("P,n,k", [(300, 37, 7), (4096, 50, 20), (17, 1, 32), (300, 130, 9), (257, 64, 24),
+                                   (1000, 65, 17)])
 def test_reconstruct_parity(torch, F, h, dt, P, n, k):
     _say(f"reconstruct P={P} n={n} k={k} {dt}")
     rng = np.random.default_rng(P + n + k)
